@@ -1,0 +1,145 @@
+"""Pins of the oracle against what the cell models and the paper fix.
+
+* resting state: F(X*) = 0, stable, and a fixed point of the time stepper;
+* TT06: the unpaced fixed point lies on the charge-invariant level of the
+  published initial conditions and long-time integration (scipy BDF, an
+  independent integrator) converges to it;
+* voltage clamp: with V frozen every voltage gate obeys a linear ODE, so the
+  stepper's result is known exactly: backward Euler products without sweeps
+  and the Lobatto IIIA (Pade) amplification after many sweeps;
+* single-cell action potential after a suprathreshold stimulus: upstroke,
+  overshoot and an APD90 window.  The paper reports tissue biomarkers only
+  (section 4, tables lr_bio and tp_bio: APD90 47.7 ms for LR91 with its
+  modified conductances, 353.5 ms for TP06); a single cell repolarises
+  without electrotonic load, so the windows below are wide and the LR91
+  window allows for the single-cell plateau being longer than the tissue one.
+"""
+import numpy as np
+import pytest
+from scipy.integrate import solve_ivp
+
+from oracle import lr91, rest, tt06
+from oracle.lobatto import nodes
+from oracle.models import LR91, LR91_ORIGINAL, TT06
+from oracle.sdc import advance
+
+ZERO = np.zeros(1)
+
+
+def test_lr91_rest_state():
+    x = rest.lr91_rest()
+    F, J = LR91.FJ(x[:, None], ZERO, ZERO)
+    assert np.max(np.abs(F[:, 0]) * 1.0) < 1e-12
+    assert np.max(np.linalg.eigvals(J[0]).real) < 0.0
+    assert -86.0 < x[0] < -83.0
+    X, st = advance(LR91, x[:, None], dt=0.05, n_steps=200, n_nodes=3, n_sweeps=2)
+    assert np.max(np.abs(X[:, 0] - x) / np.maximum(np.abs(x), LR91.newton_scale)) < 1e-9
+    assert st.n_nonconverged == 0
+
+
+def test_tt06_published_state_is_quiescent():
+    x = tt06.published_initial()
+    F = TT06.F(x[:, None], ZERO, ZERO)[:, 0]
+    assert abs(F[0]) < 2e-3            # mV/ms
+    assert np.max(np.abs(F[6:])) < 5e-3  # gates, 1/ms
+
+
+def test_tt06_unpaced_fixed_point():
+    x0 = tt06.published_initial()
+    f = lambda t, y: TT06.F(y[:, None], ZERO, ZERO)[:, 0]
+    jac = lambda t, y: TT06.FJ(y[:, None], ZERO, ZERO)[1][0]
+    sol = solve_ivp(f, (0.0, 1e7), x0, method="BDF", jac=jac, rtol=1e-10, atol=1e-12)
+    assert sol.status == 0
+    x_end = sol.y[:, -1]
+    level = rest.tt06_charge(x0)
+    xs = rest.tt06_unpaced_fixed_point(x_end, level)
+    F = TT06.F(xs[:, None], ZERO, ZERO)[:, 0]
+    assert np.max(np.abs(F)) < 1e-13
+    assert rest.tt06_charge(xs) == pytest.approx(level, rel=1e-14)
+    np.testing.assert_allclose(x_end, xs, rtol=1e-5, atol=1e-9)
+    assert -88.0 < xs[0] < -85.0
+
+
+def _clamped_gate_check(model, X0, gates, kin, K, expect_factor):
+    dt, M, n = 0.1, 3, 30
+    X, _ = advance(model, X0, dt=dt, n_steps=n, n_nodes=M, n_sweeps=K, clamp_v=True, tol=1e-14)
+    for g in gates:
+        i = model.state_names.index(g)
+        g_inf, rate = kin[g]
+        R = expect_factor(-rate * dt, dt, M)
+        expect = g_inf + (X0[i] - g_inf) * R ** n
+        np.testing.assert_allclose(X[i], expect, rtol=1e-11, atol=1e-14, err_msg=g)
+
+
+def _be_product(z, dt, M):
+    dtau = np.diff(nodes(M))
+    return np.prod([1.0 / (1.0 - z * d) for d in dtau], axis=0)
+
+
+def _pade3(z, dt, M):
+    return (1 + z / 2 + z * z / 12) / (1 - z / 2 + z * z / 12)
+
+
+@pytest.mark.parametrize("K,factor", [(0, _be_product), (50, _pade3)], ids=["K0-BE", "Kinf-Pade"])
+def test_lr91_voltage_clamp_gates(K, factor):
+    V = np.array([-30.0, 10.0, -60.0])
+    X0 = np.tile(rest.lr91_rest()[:, None], (1, 3))
+    X0[0] = V
+    r = lr91.rates(V)
+    kin = {g: (r["a" + g] / (r["a" + g] + r["b" + g]), r["a" + g] + r["b" + g]) for g in lr91.GATES}
+    _clamped_gate_check(LR91, X0, lr91.GATES, kin, K, factor)
+
+
+@pytest.mark.parametrize("K,factor", [(0, _be_product), (50, _pade3)], ids=["K0-BE", "Kinf-Pade"])
+def test_tt06_voltage_clamp_gates(K, factor):
+    V = np.array([-30.0, 10.0, -70.0])
+    X0 = np.tile(tt06.published_initial()[:, None], (1, 3))
+    X0[0] = V
+    g = tt06.gate_kinetics(V)
+    kin = {k: (g[k + "_inf"], 1.0 / g[k + "_tau"]) for k in tt06.V_GATES}
+    _clamped_gate_check(TT06, X0, tt06.V_GATES, kin, K, factor)
+
+
+def action_potential(model, x0, amp, dur, T, M=3, K=2, dt_fast=0.05, t_fast=10.0, dt_slow=0.5):
+    """Single-cell AP: fine steps through stimulus and upstroke, coarse steps after."""
+    X = x0[:, None].copy()
+    t, V = [0.0], [X[0, 0]]
+    while t[-1] < T - 1e-9:
+        dt = dt_fast if t[-1] < t_fast - 1e-9 else dt_slow
+        X, _ = advance(model, X, t0=t[-1], dt=dt, n_steps=1, n_nodes=M, n_sweeps=K,
+                       i_stim=np.array([amp]), stim_on=0.0, stim_off=dur)
+        t.append(t[-1] + dt)
+        V.append(X[0, 0])
+    t, V = np.array(t), np.array(V)
+    peak_i = int(np.argmax(V))
+    slope = np.diff(V) / np.diff(t)
+    up_i = int(np.argmax(slope))
+    v90 = V.max() - 0.9 * (V.max() - V[0])
+    below = np.nonzero(V[peak_i:] < v90)[0]
+    apd90 = t[peak_i + below[0]] - t[up_i] if len(below) else np.inf
+    return V.max(), slope.max(), apd90
+
+
+@pytest.mark.slow
+def test_lr91_paper_set_action_potential():
+    peak, dvdt, apd = action_potential(LR91, rest.lr91_rest(), -80.0, 1.0, 130.0)
+    assert 10.0 < peak < 60.0
+    assert dvdt > 50.0          # mV/ms = V/s
+    assert 40.0 < apd < 110.0
+
+
+@pytest.mark.slow
+def test_lr91_original_set_action_potential():
+    x = rest.solve_rest(LR91_ORIGINAL, lr91.rest_guess())
+    peak, dvdt, apd = action_potential(LR91_ORIGINAL, x, -80.0, 1.0, 450.0)
+    assert 40.0 < peak < 70.0
+    assert dvdt > 200.0
+    assert 300.0 < apd < 420.0
+
+
+@pytest.mark.slow
+def test_tt06_epi_action_potential():
+    peak, dvdt, apd = action_potential(TT06, tt06.published_initial(), -52.0, 1.0, 380.0)
+    assert 20.0 < peak < 60.0
+    assert dvdt > 100.0
+    assert 250.0 < apd < 340.0
