@@ -1,0 +1,204 @@
+/*
+ * ionic_sdc.h -- C ABI of the MI355X reaction + SDC library (libionic_sdc.so).
+ *
+ * What it computes.  The per-vertex ODE stage of the partitioned bidomain
+ * strategy with spectral deferred correction (paper section 3.3.2): with the
+ * extracellular coupling held fixed over a step (here: a fixed per-vertex
+ * diffusion current I_diff), every mesh vertex carries the state
+ * X = (v, w, c) of equation genODE and integrates dX/dt = F(X) with M~ = I,
+ *     F = [ -(I_ion + I_stim) + I_diff ; G(v, w) ; S(v, w, c) ]
+ * (equations parabolic, odes_con, odes).  One time step runs a
+ * backward-Euler local-Newton predictor over the M Gauss-Lobatto
+ * sub-intervals and K linearised implicit corrections (equations residual,
+ * sdc_ode, sdc; M = 2, K = 1 is the paper's trapezoidal correction).  The
+ * local Jacobian uses exact derivatives (text after equation rb_system) and a
+ * sparsity fixed at compile time (the paper's CTSM technique).
+ *
+ * Conventions shared by every entry point.
+ *  - Every function returns an int status: IONIC_OK (0) or a negative
+ *    IONIC_E* code; ionic_last_error() gives a message (thread-local).  No
+ *    C++ exception crosses the ABI.  Invalid arguments are rejected before
+ *    any HIP call is made.
+ *  - Units: V in mV, t in ms, currents in uA/cm^2 (= pA/pF with
+ *    C_m = 1 uF/cm^2 in the voltage equation), concentrations in mM.
+ *    I_stim follows the cell-model convention dV/dt = -(I_ion + I_stim), so a
+ *    negative amplitude depolarises (the paper's +100 uA/cm^2 is -100 here).
+ *  - Device pointers are HIP device addresses on the current device; the
+ *    caller owns them and keeps them alive until the work that uses them has
+ *    completed on the stream.  `hip_stream` is a hipStream_t passed as
+ *    void* (NULL = the null stream).  Work is enqueued asynchronously unless
+ *    a function says it synchronises.
+ *  - State layout in HBM ("SoA planes"): plane i holds state i of all
+ *    vertices, planes in the order of ionic_state_name(model, i).  A plane
+ *    has ionic_plane_stride(n) elements (n rounded up to a multiple of 64).
+ *    IONIC_FP64: every plane is double.  IONIC_MIXED: the first
+ *    ionic_n_fp64_states(model) planes (V and the intracellular
+ *    concentrations) are double and the remaining ones (gates) are float.
+ *  - A handle is not thread-safe; different handles may be used
+ *    concurrently on different streams.
+ */
+#ifndef IONIC_SDC_H
+#define IONIC_SDC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Cell models (paper section 2).  IONIC_LR91: Luo-Rudy 1991, 8 states, with
+ * the paper's modified conductances G_si = 0.02, G_Na = 4.0, G_K = 0.423
+ * (section 4) unless params override them.  IONIC_TT06_EPI: ten Tusscher-
+ * Panfilov 2006 epicardial cell, 19 states.  The two test models are scalar
+ * problems with closed forms used to check the SDC machinery:
+ * IONIC_TEST_LINEAR y' = lam*y + b + I_diff (params lam, b) and
+ * IONIC_TEST_LOGISTIC y' = rate*y*(1-y) + I_diff (param rate). */
+enum { IONIC_LR91 = 1, IONIC_TT06_EPI = 2, IONIC_TEST_LINEAR = 90, IONIC_TEST_LOGISTIC = 91 };
+
+/* IONIC_FP64: everything in double.  IONIC_MIXED: F, J and the sparse solve
+ * in float; V, the intracellular concentrations, the SDC residual and their
+ * updates in double; gates stored and updated in float. */
+enum { IONIC_FP64 = 0, IONIC_MIXED = 1 };
+
+enum {
+  IONIC_OK = 0,
+  IONIC_EINVAL = -1,       /* bad argument (null pointer, size, range)          */
+  IONIC_EUNSUPPORTED = -2, /* model / precision / node count not built          */
+  IONIC_EHIP = -3,         /* a HIP runtime call failed (message has the code)  */
+  IONIC_ENOMEM = -4,       /* a library-internal allocation failed              */
+  IONIC_ESTATE = -5        /* handle used in a wrong state (e.g. mixed batch)   */
+};
+
+#define IONIC_MAX_NODES 5   /* Gauss-Lobatto nodes per step: 2..5 */
+#define IONIC_MAX_SWEEPS 16 /* SDC corrections per step: 0..16   */
+
+typedef struct ionic_sim ionic_sim; /* opaque, owned by the library */
+
+typedef struct {
+  int64_t n_vertices;   /* N >= 1 */
+  int32_t model;        /* IONIC_LR91, ... */
+  int32_t precision;    /* IONIC_FP64 or IONIC_MIXED */
+  double newton_tol;    /* predictor stop: max_i |delta_i|/max(|Y_i|, scale_i) <= tol; >= 0.
+                           IONIC_MIXED uses max(tol, 1e-6): an fp32 F cannot resolve less. */
+  int32_t newton_maxit; /* 1..64; the last iterate is kept and counted when reached */
+  int32_t n_params;     /* number of entries in params (0 = defaults) */
+  const double* params; /* host; overrides of the model's leading parameters, see
+                           ionic_param_name(); NULL/0 = defaults */
+} ionic_config;
+
+typedef struct {
+  int64_t vertex_steps;      /* sum over launches of N * n_steps                  */
+  int64_t newton_iters;      /* Newton iterations summed over vertices and nodes  */
+  int64_t newton_solves;     /* predictor solves (vertices x steps x (M-1))       */
+  int64_t n_nonconverged;    /* predictor solves that stopped at newton_maxit     */
+  int64_t n_nonfinite;       /* vertices whose state was non-finite after a launch */
+  int32_t newton_it_max;     /* largest iteration count of one solve              */
+  int32_t reserved;
+} ionic_stats;
+
+/* ---- model description (host only; no GPU needed) ------------------------ */
+
+/* Number of states of `model` (8, 19, 1, 1), or IONIC_EUNSUPPORTED. */
+int ionic_n_states(int model);
+
+/* Number of leading planes kept in double under IONIC_MIXED (2 for LR91: V, Cai;
+ * 6 for TT06: V, Cai, CaSR, CaSS, Nai, Ki; 1 for the test models). */
+int ionic_n_fp64_states(int model);
+
+/* Name of state `idx` ("V", "Cai", ...), i.e. the plane order; NULL if out of range. */
+const char* ionic_state_name(int model, int idx);
+
+/* Number of overridable parameters and the name of parameter `idx`. */
+int ionic_n_params(int model);
+const char* ionic_param_name(int model, int idx);
+
+/* Elements per plane for N vertices: N rounded up to a multiple of 64. */
+int64_t ionic_plane_stride(int64_t n_vertices);
+
+/* Bytes of device memory the caller must provide for the state of N vertices;
+ * 0 for an unknown model/precision or N < 1. */
+size_t ionic_state_bytes(int model, int precision, int64_t n_vertices);
+
+/* Gauss-Lobatto nodes c[0..M-1] on [0, 1] and the integration matrix
+ * S[m*M + j] = integral_{c_m}^{c_{m+1}} l_j(s) ds (m < M-1), l_j the Lagrange
+ * basis of node j.  M = 2 gives the trapezoid [1/2, 1/2] of equation sdc.
+ * Host only.  c needs M doubles, S needs (M-1)*M; either may be NULL. */
+int ionic_lobatto(int n_nodes, double* c, double* S);
+
+/* ---- lifetime -------------------------------------------------------------- */
+
+/* Create a simulation over a caller-owned device buffer `state_dev` of
+ * `state_bytes` >= ionic_state_bytes(...) bytes (it must outlive the handle)
+ * and load the initial state.  x0: n_states x N doubles, row i = state i of
+ * every vertex (FP64 SoA, plane order), on the host (x0_on_device = 0) or
+ * on the device (1); it is converted into the precision layout on the GPU.
+ * x0 must not be NULL.  Enqueues on hip_stream and synchronises it before
+ * returning (the host copy of x0 may be released afterwards). */
+int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t state_bytes,
+               const double* x0, int x0_on_device, void* hip_stream);
+
+/* Release the handle and its library-owned memory (not the state buffer).
+ * Synchronises the device first.  NULL is ignored. */
+void ionic_destroy(ionic_sim* sim);
+
+/* ---- the hot path ------------------------------------------------------------ */
+
+/* Advance every vertex by n_steps steps of size dt (t_n = t0 + n*dt):
+ * per step the predictor and n_sweeps corrections on n_nodes Gauss-Lobatto
+ * nodes, all fused in one kernel launch with the state held in registers.
+ *  i_stim_dev: N doubles (stimulus amplitude per vertex) or NULL (none);
+ *              step n is stimulated iff stim_t_on <= t0 + (n + 1/2) dt < stim_t_off.
+ *  i_diff_dev: N doubles, fixed diffusion current added to dV/dt, or NULL (0).
+ * n_steps >= 0, dt > 0 and finite, 2 <= n_nodes <= IONIC_MAX_NODES,
+ * 0 <= n_sweeps <= IONIC_MAX_SWEEPS.  Asynchronous.  Newton non-convergence
+ * and non-finite states are not errors: they are counted in the stats. */
+int reaction_sdc_step(ionic_sim* sim, double t0, double dt, int n_steps, int n_nodes,
+                      int n_sweeps, const double* i_stim_dev, double stim_t_on,
+                      double stim_t_off, const double* i_diff_dev, void* hip_stream);
+
+/* Store the step inputs of `sim` for reaction_sdc_step_batch (same meaning as
+ * the arguments of reaction_sdc_step).  The batch advances the handle's own
+ * step counter, so chunks of a long run keep t_n = t0 + n*dt exact. */
+int ionic_set_inputs(ionic_sim* sim, double t0, double dt, int n_nodes, int n_sweeps,
+                     const double* i_stim_dev, double stim_t_on, double stim_t_off,
+                     const double* i_diff_dev);
+
+/* Continuous-batching entry: advance n_sims handles by n_steps[i] steps each
+ * in as few launches as possible (one per group of up to 24 handles).  All
+ * handles must share model, precision, n_nodes, parameters and Newton
+ * settings (else IONIC_ESTATE).  Each vertex computes exactly what a
+ * reaction_sdc_step call on its own handle computes (bit-identical). */
+int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_sims,
+                            void* hip_stream);
+
+/* Copy states of vertices [first, first+count) into out: n_states x count
+ * doubles (row i = state i), on the host (out_on_device = 0) or the device.
+ * Mixed layouts are widened to double on the GPU.  Synchronises hip_stream. */
+int state_readback(ionic_sim* sim, double* out, int64_t first, int64_t count,
+                   int out_on_device, void* hip_stream);
+
+/* Set every voltage-dependent gate to its steady state at the vertex's
+ * current V (TT06: fCass to its steady state at the current CaSS); other
+ * states unchanged.  Builds initial fields such as spiral waves. Asynchronous. */
+int ionic_gates_to_steady_state(ionic_sim* sim, void* hip_stream);
+
+/* Cumulative statistics since init.  Synchronises the device. */
+int ionic_get_stats(ionic_sim* sim, ionic_stats* out);
+int ionic_reset_stats(ionic_sim* sim);
+
+/* Debug/test: F and the Jacobian at the current state of one vertex, evaluated
+ * by the same device code as the hot path (float under IONIC_MIXED, widened).
+ * F_out: n doubles, J_out: n*n doubles row-major (J[i*n+k] = dF_i/dX_k), host.
+ * Entries outside the compile-time pattern are returned as 0.  Synchronises. */
+int ionic_debug_jacobian(ionic_sim* sim, int64_t vertex, double i_stim, double i_diff,
+                         double* F_out, double* J_out, void* hip_stream);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* ionic_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IONIC_SDC_H */

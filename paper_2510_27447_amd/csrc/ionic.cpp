@@ -1,0 +1,476 @@
+// Host side of the C ABI declared in include/ionic_sdc.h: argument checking,
+// parameter derivation, Gauss-Lobatto nodes and quadrature, launch
+// assembly and the handle's bookkeeping.  All numerical work of the
+// reaction + SDC stage runs in the kernels of sdc_kernel.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ionic_sdc.h"
+#include "kernel_ops.h"
+
+using ionic::DevStats;
+using ionic::kBlock;
+using ionic::kMaxBatch;
+using ionic::kMaxNodes;
+using ionic::LaunchCommon;
+using ionic::ModelOps;
+using ionic::SimDesc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(IONIC_EHIP, std::string(what) + ": " + hipGetErrorName(e) + " (" +
+                              hipGetErrorString(e) + ")");
+}
+
+#define IONIC_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);     \
+  } while (0)
+
+const ModelOps* ops_for(int model) {
+  switch (model) {
+    case IONIC_LR91: return &ionic::kOpsLR91;
+    case IONIC_TT06_EPI: return &ionic::kOpsTT06;
+    case IONIC_TEST_LINEAR: return &ionic::kOpsTestLinear;
+    case IONIC_TEST_LOGISTIC: return &ionic::kOpsTestLogistic;
+    default: return nullptr;
+  }
+}
+
+bool valid_precision(int p) { return p == IONIC_FP64 || p == IONIC_MIXED; }
+
+int64_t stride_of(int64_t n) { return (n + 63) / 64 * 64; }
+
+size_t bytes_of(const ModelOps* o, int precision, int64_t n) {
+  const size_t s = size_t(stride_of(n));
+  if (precision == IONIC_FP64) return size_t(o->n_states) * s * 8;
+  return size_t(o->n_fp64) * s * 8 + size_t(o->n_states - o->n_fp64) * s * 4;
+}
+
+// Gauss-Lobatto nodes on [0, 1]: endpoints plus the roots of P'_{M-1}
+// mapped from [-1, 1] (closed forms for M <= 5).
+void lobatto_nodes(int M, double* c) {
+  c[0] = 0.0;
+  c[M - 1] = 1.0;
+  if (M == 3) c[1] = 0.5;
+  if (M == 4) {
+    const double s5 = std::sqrt(5.0);
+    c[1] = (5.0 - s5) / 10.0;
+    c[2] = (5.0 + s5) / 10.0;
+  }
+  if (M == 5) {
+    const double s21 = std::sqrt(21.0);
+    c[1] = (7.0 - s21) / 14.0;
+    c[2] = 0.5;
+    c[3] = (7.0 + s21) / 14.0;
+  }
+}
+
+// S[m][j] = integral_{c_m}^{c_{m+1}} l_j(s) ds by 5-point Gauss-Legendre
+// quadrature, exact for the degree <= 4 Lagrange polynomials.
+void lobatto_matrix(int M, const double* c, double* S /* (M-1) x M */) {
+  const double a = std::sqrt(5.0 - 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+  const double b = std::sqrt(5.0 + 2.0 * std::sqrt(10.0 / 7.0)) / 3.0;
+  const double wa = (322.0 + 13.0 * std::sqrt(70.0)) / 900.0;
+  const double wb = (322.0 - 13.0 * std::sqrt(70.0)) / 900.0;
+  const double gx[5] = {-b, -a, 0.0, a, b};
+  const double gw[5] = {wb, wa, 128.0 / 225.0, wa, wb};
+  for (int m = 0; m < M - 1; ++m) {
+    const double lo = c[m], hi = c[m + 1], half = 0.5 * (hi - lo), mid = 0.5 * (hi + lo);
+    for (int j = 0; j < M; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < 5; ++q) {
+        const double s = mid + half * gx[q];
+        double l = 1.0;
+        for (int k = 0; k < M; ++k)
+          if (k != j) l *= (s - c[k]) / (c[j] - c[k]);
+        acc += gw[q] * l;
+      }
+      S[m * M + j] = half * acc;
+    }
+  }
+}
+
+}  // namespace
+
+struct ionic_sim {
+  const ModelOps* ops = nullptr;
+  int model = 0;
+  int precision = 0;
+  int64_t n = 0;
+  int64_t stride = 0;
+  void* state = nullptr;
+  std::vector<double> raw;
+  alignas(16) unsigned char p64[1024];
+  alignas(16) unsigned char p32[1024];
+  double tol = 0.0;
+  int maxit = 0;
+  DevStats* stats = nullptr;
+  // inputs for the batched entry
+  bool inputs_set = false;
+  double t0 = 0.0, dt = 0.0, t_on = 0.0, t_off = 0.0;
+  int M = 0, K = 0;
+  const double* i_stim = nullptr;
+  const double* i_diff = nullptr;
+  long long step_offset = 0;
+
+  const void* params() const { return precision == IONIC_FP64 ? (const void*)p64 : (const void*)p32; }
+};
+
+namespace {
+
+void fill_quadrature(int M, LaunchCommon& c) {
+  std::memset(&c, 0, sizeof(c));
+  double nodes[kMaxNodes], S[(kMaxNodes - 1) * kMaxNodes];
+  lobatto_nodes(M, nodes);
+  lobatto_matrix(M, nodes, S);
+  for (int m = 0; m < M - 1; ++m) {
+    c.dc[m] = nodes[m + 1] - nodes[m];
+    for (int j = 0; j < M; ++j) c.S[m][j] = S[m * M + j];
+  }
+}
+
+SimDesc desc_of(const ionic_sim* s, double t0, double dt, const double* stim, double t_on,
+                double t_off, const double* diff, long long offset, int n_steps, int K,
+                int first_block) {
+  SimDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.state = s->state;
+  d.n = s->n;
+  d.stride = s->stride;
+  d.i_stim = stim;
+  d.i_diff = diff;
+  d.t0 = t0;
+  d.dt = dt;
+  d.t_on = t_on;
+  d.t_off = t_off;
+  d.step_offset = offset;
+  d.n_steps = n_steps;
+  d.n_sweeps = K;
+  d.stats = s->stats;
+  d.first_block = first_block;
+  return d;
+}
+
+int check_step_args(double t0, double dt, int n_steps, int n_nodes, int n_sweeps, double t_on,
+                    double t_off) {
+  if (n_steps < 0) return fail(IONIC_EINVAL, "n_steps must be >= 0");
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(IONIC_EINVAL, "dt must be positive and finite");
+  if (!std::isfinite(t0)) return fail(IONIC_EINVAL, "t0 must be finite");
+  if (n_nodes < 2 || n_nodes > IONIC_MAX_NODES)
+    return fail(IONIC_EUNSUPPORTED, "n_nodes must be in [2, " + std::to_string(IONIC_MAX_NODES) + "]");
+  if (n_sweeps < 0 || n_sweeps > IONIC_MAX_SWEEPS)
+    return fail(IONIC_EINVAL, "n_sweeps must be in [0, " + std::to_string(IONIC_MAX_SWEEPS) + "]");
+  if (std::isnan(t_on) || std::isnan(t_off)) return fail(IONIC_EINVAL, "stimulus window is NaN");
+  return IONIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ionic_last_error(void) { return g_err.c_str(); }
+
+int ionic_n_states(int model) {
+  const ModelOps* o = ops_for(model);
+  return o ? o->n_states : fail(IONIC_EUNSUPPORTED, "unknown model");
+}
+
+int ionic_n_fp64_states(int model) {
+  const ModelOps* o = ops_for(model);
+  return o ? o->n_fp64 : fail(IONIC_EUNSUPPORTED, "unknown model");
+}
+
+const char* ionic_state_name(int model, int idx) {
+  const ModelOps* o = ops_for(model);
+  if (!o || idx < 0 || idx >= o->n_states) return nullptr;
+  return o->state_names[idx];
+}
+
+int ionic_n_params(int model) {
+  const ModelOps* o = ops_for(model);
+  return o ? o->n_params : fail(IONIC_EUNSUPPORTED, "unknown model");
+}
+
+const char* ionic_param_name(int model, int idx) {
+  const ModelOps* o = ops_for(model);
+  if (!o || idx < 0 || idx >= o->n_params) return nullptr;
+  return o->param_names[idx];
+}
+
+int64_t ionic_plane_stride(int64_t n) { return n < 1 ? 0 : stride_of(n); }
+
+size_t ionic_state_bytes(int model, int precision, int64_t n) {
+  const ModelOps* o = ops_for(model);
+  if (!o || !valid_precision(precision) || n < 1) return 0;
+  return bytes_of(o, precision, n);
+}
+
+int ionic_lobatto(int M, double* c, double* S) {
+  if (M < 2 || M > IONIC_MAX_NODES) return fail(IONIC_EUNSUPPORTED, "n_nodes must be in [2, 5]");
+  double nodes[kMaxNodes];
+  lobatto_nodes(M, nodes);
+  if (c) std::memcpy(c, nodes, sizeof(double) * M);
+  if (S) lobatto_matrix(M, nodes, S);
+  return IONIC_OK;
+}
+
+int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t state_bytes,
+               const double* x0, int x0_on_device, void* hip_stream) {
+  if (!out) return fail(IONIC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfg) return fail(IONIC_EINVAL, "cfg is NULL");
+  const ModelOps* o = ops_for(cfg->model);
+  if (!o) return fail(IONIC_EUNSUPPORTED, "unknown model " + std::to_string(cfg->model));
+  if (!valid_precision(cfg->precision)) return fail(IONIC_EUNSUPPORTED, "unknown precision");
+  if (cfg->n_vertices < 1) return fail(IONIC_EINVAL, "n_vertices must be >= 1");
+  if (cfg->n_vertices > (int64_t(1) << 36)) return fail(IONIC_EINVAL, "n_vertices too large");
+  if (!(cfg->newton_tol >= 0.0) || !std::isfinite(cfg->newton_tol))
+    return fail(IONIC_EINVAL, "newton_tol must be finite and >= 0");
+  if (cfg->newton_maxit < 1 || cfg->newton_maxit > 64)
+    return fail(IONIC_EINVAL, "newton_maxit must be in [1, 64]");
+  if (cfg->n_params < 0 || cfg->n_params > o->n_params)
+    return fail(IONIC_EINVAL, "n_params out of range (max " + std::to_string(o->n_params) + ")");
+  if (cfg->n_params > 0 && !cfg->params) return fail(IONIC_EINVAL, "params is NULL");
+  if (!state_dev) return fail(IONIC_EINVAL, "state_dev is NULL");
+  const size_t need = bytes_of(o, cfg->precision, cfg->n_vertices);
+  if (state_bytes < need)
+    return fail(IONIC_EINVAL, "state buffer too small: need " + std::to_string(need) + " bytes");
+  if (!x0) return fail(IONIC_EINVAL, "x0 is NULL");
+  if (o->params_bytes[0] > 1024 || o->params_bytes[1] > 1024)
+    return fail(IONIC_EUNSUPPORTED, "parameter block too large");
+
+  ionic_sim* s = new ionic_sim();
+  s->ops = o;
+  s->model = cfg->model;
+  s->precision = cfg->precision;
+  s->n = cfg->n_vertices;
+  s->stride = stride_of(s->n);
+  s->state = state_dev;
+  s->raw.assign(o->param_defaults, o->param_defaults + o->n_raw);
+  for (int i = 0; i < cfg->n_params; ++i) s->raw[i] = cfg->params[i];
+  o->derive(s->raw.data(), s->p64, s->p32);
+  s->tol = cfg->precision == IONIC_MIXED ? std::max(cfg->newton_tol, 1e-6) : cfg->newton_tol;
+  s->maxit = cfg->newton_maxit;
+
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  auto cleanup = [&](int rc) {
+    if (s->stats) (void)hipFree(s->stats);
+    delete s;
+    return rc;
+  };
+  hipError_t e = hipMalloc(&s->stats, sizeof(DevStats));
+  if (e != hipSuccess) {
+    s->stats = nullptr;
+    return cleanup(hip_fail(e, "hipMalloc(stats)"));
+  }
+  e = hipMemsetAsync(s->stats, 0, sizeof(DevStats), st);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemsetAsync(stats)"));
+
+  const double* src = x0;
+  double* staging = nullptr;
+  const size_t x0_bytes = size_t(o->n_states) * size_t(s->n) * sizeof(double);
+  if (!x0_on_device) {
+    e = hipMalloc(&staging, x0_bytes);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(x0 staging)"));
+    e = hipMemcpyAsync(staging, x0, x0_bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) {
+      (void)hipFree(staging);
+      return cleanup(hip_fail(e, "hipMemcpyAsync(x0)"));
+    }
+    src = staging;
+  }
+  e = o->pack(s->precision, src, s->n, s->state, s->stride, 0, s->n, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (staging) (void)hipFree(staging);
+  if (e != hipSuccess) return cleanup(hip_fail(e, "pack initial state"));
+  *out = s;
+  return IONIC_OK;
+}
+
+void ionic_destroy(ionic_sim* s) {
+  if (!s) return;
+  (void)hipDeviceSynchronize();
+  if (s->stats) (void)hipFree(s->stats);
+  delete s;
+}
+
+int reaction_sdc_step(ionic_sim* s, double t0, double dt, int n_steps, int n_nodes, int n_sweeps,
+                      const double* i_stim_dev, double stim_t_on, double stim_t_off,
+                      const double* i_diff_dev, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_step_args(t0, dt, n_steps, n_nodes, n_sweeps, stim_t_on, stim_t_off);
+  if (rc != IONIC_OK) return rc;
+  if (n_steps == 0) return IONIC_OK;
+  LaunchCommon c;
+  fill_quadrature(n_nodes, c);
+  c.tol = s->tol;
+  c.maxit = s->maxit;
+  c.n_sims = 1;
+  c.sims[0] = desc_of(s, t0, dt, i_stim_dev, stim_t_on, stim_t_off, i_diff_dev, 0, n_steps,
+                      n_sweeps, 0);
+  const int blocks = int((s->n + kBlock - 1) / kBlock);
+  hipError_t e = (s->precision == IONIC_FP64 ? s->ops->sdc64 : s->ops->sdc32)(
+      n_nodes, s->params(), c, blocks, static_cast<hipStream_t>(hip_stream));
+  if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel");
+  return IONIC_OK;
+}
+
+int ionic_set_inputs(ionic_sim* s, double t0, double dt, int n_nodes, int n_sweeps,
+                     const double* i_stim_dev, double stim_t_on, double stim_t_off,
+                     const double* i_diff_dev) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_step_args(t0, dt, 0, n_nodes, n_sweeps, stim_t_on, stim_t_off);
+  if (rc != IONIC_OK) return rc;
+  s->inputs_set = true;
+  s->t0 = t0;
+  s->dt = dt;
+  s->M = n_nodes;
+  s->K = n_sweeps;
+  s->i_stim = i_stim_dev;
+  s->t_on = stim_t_on;
+  s->t_off = stim_t_off;
+  s->i_diff = i_diff_dev;
+  s->step_offset = 0;
+  return IONIC_OK;
+}
+
+int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_sims,
+                            void* hip_stream) {
+  if (n_sims < 0) return fail(IONIC_EINVAL, "n_sims must be >= 0");
+  if (n_sims == 0) return IONIC_OK;
+  if (!sims || !n_steps) return fail(IONIC_EINVAL, "sims or n_steps is NULL");
+  const ionic_sim* s0 = sims[0];
+  if (!s0) return fail(IONIC_EINVAL, "sims[0] is NULL");
+  for (int i = 0; i < n_sims; ++i) {
+    const ionic_sim* s = sims[i];
+    if (!s) return fail(IONIC_EINVAL, "sims[" + std::to_string(i) + "] is NULL");
+    if (n_steps[i] < 0) return fail(IONIC_EINVAL, "n_steps[" + std::to_string(i) + "] < 0");
+    if (!s->inputs_set)
+      return fail(IONIC_ESTATE, "sims[" + std::to_string(i) + "]: ionic_set_inputs not called");
+    if (s->model != s0->model || s->precision != s0->precision || s->M != s0->M ||
+        s->tol != s0->tol || s->maxit != s0->maxit || s->raw != s0->raw)
+      return fail(IONIC_ESTATE, "batched handles must share model, precision, n_nodes, "
+                                "parameters and Newton settings");
+    for (int k = 0; k < i; ++k)
+      if (sims[k] == s) return fail(IONIC_EINVAL, "a handle appears twice in the batch");
+  }
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  LaunchCommon c;
+  fill_quadrature(s0->M, c);
+  c.tol = s0->tol;
+  c.maxit = s0->maxit;
+  int i = 0;
+  while (i < n_sims) {
+    int cnt = 0, blocks = 0;
+    for (; i < n_sims && cnt < kMaxBatch; ++i) {
+      ionic_sim* s = sims[i];
+      if (n_steps[i] == 0) continue;
+      c.sims[cnt] = desc_of(s, s->t0, s->dt, s->i_stim, s->t_on, s->t_off, s->i_diff,
+                            s->step_offset, n_steps[i], s->K, blocks);
+      blocks += int((s->n + kBlock - 1) / kBlock);
+      ++cnt;
+    }
+    if (cnt == 0) continue;
+    c.n_sims = cnt;
+    hipError_t e = (s0->precision == IONIC_FP64 ? s0->ops->sdc64 : s0->ops->sdc32)(
+        s0->M, s0->params(), c, blocks, st);
+    if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (batch)");
+  }
+  for (int k = 0; k < n_sims; ++k) sims[k]->step_offset += n_steps[k];
+  return IONIC_OK;
+}
+
+int state_readback(ionic_sim* s, double* out, int64_t first, int64_t count, int out_on_device,
+                   void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (!out) return fail(IONIC_EINVAL, "out is NULL");
+  if (first < 0 || count < 0 || first + count > s->n)
+    return fail(IONIC_EINVAL, "vertex range out of bounds");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  if (count == 0) return IONIC_OK;
+  const size_t bytes = size_t(s->ops->n_states) * size_t(count) * sizeof(double);
+  if (out_on_device) {
+    IONIC_HIP(s->ops->unpack(s->precision, s->state, s->stride, first, count, out, count, st));
+    IONIC_HIP(hipStreamSynchronize(st));
+    return IONIC_OK;
+  }
+  double* tmp = nullptr;
+  IONIC_HIP(hipMalloc(&tmp, bytes));
+  hipError_t e = s->ops->unpack(s->precision, s->state, s->stride, first, count, tmp, count, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "state_readback");
+  return IONIC_OK;
+}
+
+int ionic_gates_to_steady_state(ionic_sim* s, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  IONIC_HIP(s->ops->steady(s->precision, s->params(), s->state, s->stride, s->n,
+                           static_cast<hipStream_t>(hip_stream)));
+  return IONIC_OK;
+}
+
+int ionic_get_stats(ionic_sim* s, ionic_stats* out) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (!out) return fail(IONIC_EINVAL, "out is NULL");
+  DevStats d;
+  IONIC_HIP(hipDeviceSynchronize());
+  IONIC_HIP(hipMemcpy(&d, s->stats, sizeof(d), hipMemcpyDeviceToHost));
+  out->vertex_steps = int64_t(d.vertex_steps);
+  out->newton_iters = int64_t(d.newton_iters);
+  out->newton_solves = int64_t(d.newton_solves);
+  out->n_nonconverged = int64_t(d.nonconverged);
+  out->n_nonfinite = int64_t(d.nonfinite);
+  out->newton_it_max = int32_t(d.it_max);
+  out->reserved = 0;
+  return IONIC_OK;
+}
+
+int ionic_reset_stats(ionic_sim* s) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  IONIC_HIP(hipDeviceSynchronize());
+  IONIC_HIP(hipMemset(s->stats, 0, sizeof(DevStats)));
+  IONIC_HIP(hipDeviceSynchronize());
+  return IONIC_OK;
+}
+
+int ionic_debug_jacobian(ionic_sim* s, int64_t vertex, double i_stim, double i_diff,
+                         double* F_out, double* J_out, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (vertex < 0 || vertex >= s->n) return fail(IONIC_EINVAL, "vertex out of range");
+  if (!F_out || !J_out) return fail(IONIC_EINVAL, "F_out or J_out is NULL");
+  const int n = s->ops->n_states;
+  const size_t bytes = size_t(n + n * n) * sizeof(double);
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  double* tmp = nullptr;
+  IONIC_HIP(hipMalloc(&tmp, bytes));
+  std::vector<double> host(size_t(n + n * n));
+  hipError_t e = s->ops->debug_jac(s->precision, s->params(), s->state, s->stride, vertex, i_stim,
+                                   i_diff, tmp, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), tmp, bytes, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(tmp);
+  if (e != hipSuccess) return hip_fail(e, "ionic_debug_jacobian");
+  std::memcpy(F_out, host.data(), sizeof(double) * n);
+  std::memcpy(J_out, host.data() + n, sizeof(double) * n * n);
+  return IONIC_OK;
+}
+
+}  // extern "C"

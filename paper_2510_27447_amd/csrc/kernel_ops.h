@@ -1,0 +1,53 @@
+// Type-erased launch table of one cell model: the host library dispatches on
+// (model, precision, node count) at run time through these entries; each
+// model's kernels are instantiated in a translation unit of their own.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "sdc_kernel.h"
+
+namespace ionic {
+
+struct LaunchCommon {
+  double S[kMaxNodes - 1][kMaxNodes];
+  double dc[kMaxNodes - 1];
+  double tol;
+  int maxit;
+  int n_sims;
+  SimDesc sims[kMaxBatch];
+};
+
+struct ModelOps {
+  int n_states;
+  int n_fp64;  // leading planes in double under the mixed layout
+  int n_params;
+  const char* const* param_names;
+  const double* param_defaults;  // n_params (+ trailing fixed entries)
+  int n_raw;                     // length of the raw parameter vector
+  const char* const* state_names;
+  size_t params_bytes[2];        // sizeof(Params<double>), sizeof(Params<float>)
+  void (*derive)(const double* raw, void* p64, void* p32);
+  // fused step kernel, double / mixed precision policy
+  hipError_t (*sdc64)(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
+  hipError_t (*sdc32)(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
+  hipError_t (*pack)(int prec, const double* src, long long ld, void* state, long long stride,
+                     long long first, long long count, hipStream_t st);
+  hipError_t (*unpack)(int prec, const void* state, long long stride, long long first,
+                       long long count, double* dst, long long ld, hipStream_t st);
+  hipError_t (*steady)(int prec, const void* params, void* state, long long stride, long long n,
+                       hipStream_t st);
+  hipError_t (*debug_jac)(int prec, const void* params, const void* state, long long stride,
+                          long long v, double stim, double diff, double* out, hipStream_t st);
+};
+
+// The double-precision TT06 step kernel lives in a translation unit of its own,
+// compiled at a lower optimisation level (see the build script).
+hipError_t tt06_sdc64(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
+
+extern const ModelOps kOpsLR91;
+extern const ModelOps kOpsTT06;
+extern const ModelOps kOpsTestLinear;
+extern const ModelOps kOpsTestLogistic;
+
+}  // namespace ionic

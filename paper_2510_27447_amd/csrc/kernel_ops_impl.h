@@ -1,0 +1,131 @@
+// Instantiation helpers behind ModelOps (included by one .hip file per model).
+#pragma once
+
+#include "kernel_ops.h"
+
+namespace ionic {
+
+template <class Model>
+struct OpsImpl {
+  static constexpr int kAuxBlock = 256;
+
+  static void derive(const double* raw, void* p64, void* p32) {
+    *static_cast<typename Model::template Params<double>*>(p64) = Model::template derive<double>(raw);
+    *static_cast<typename Model::template Params<float>*>(p32) = Model::template derive<float>(raw);
+  }
+
+  template <class Prec, int M>
+  static hipError_t launch_m(const void* params, const LaunchCommon& c, int blocks, hipStream_t st) {
+    using P = typename Model::template Params<typename Prec::TE>;
+    LaunchArgs<P> a;
+    a.params = *static_cast<const P*>(params);
+    for (int m = 0; m < kMaxNodes - 1; ++m) {
+      a.dc[m] = c.dc[m];
+      for (int j = 0; j < kMaxNodes; ++j) a.S[m][j] = c.S[m][j];
+    }
+    a.tol = c.tol;
+    a.maxit = c.maxit;
+    a.n_sims = c.n_sims;
+    for (int s = 0; s < kMaxBatch; ++s) a.sims[s] = c.sims[s];
+    static_assert(sizeof(LaunchArgs<P>) <= 3800, "kernel arguments must fit the kernarg segment");
+    hipLaunchKernelGGL((sdc_kernel<Model, Prec, M>), dim3(blocks), dim3(kBlock), 0, st, a);
+    return hipGetLastError();
+  }
+
+  template <class Prec>
+  static hipError_t sdc_prec(int M, const void* params, const LaunchCommon& c, int blocks,
+                             hipStream_t st) {
+    switch (M) {
+      case 2: return launch_m<Prec, 2>(params, c, blocks, st);
+      case 3: return launch_m<Prec, 3>(params, c, blocks, st);
+      case 4: return launch_m<Prec, 4>(params, c, blocks, st);
+      case 5: return launch_m<Prec, 5>(params, c, blocks, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  static hipError_t sdc64(int M, const void* params, const LaunchCommon& c, int blocks,
+                          hipStream_t st) {
+    return sdc_prec<Fp64>(M, params, c, blocks, st);
+  }
+  static hipError_t sdc32(int M, const void* params, const LaunchCommon& c, int blocks,
+                          hipStream_t st) {
+    return sdc_prec<Mixed>(M, params, c, blocks, st);
+  }
+
+  static int grid(long long count) { return int((count + kAuxBlock - 1) / kAuxBlock); }
+
+  static hipError_t pack(int prec, const double* src, long long ld, void* state, long long stride,
+                         long long first, long long count, hipStream_t st) {
+    if (prec == 0)
+      hipLaunchKernelGGL((pack_kernel<Model, Fp64>), dim3(grid(count)), dim3(kAuxBlock), 0, st, src,
+                         ld, state, stride, first, count);
+    else
+      hipLaunchKernelGGL((pack_kernel<Model, Mixed>), dim3(grid(count)), dim3(kAuxBlock), 0, st,
+                         src, ld, state, stride, first, count);
+    return hipGetLastError();
+  }
+  static hipError_t unpack(int prec, const void* state, long long stride, long long first,
+                           long long count, double* dst, long long ld, hipStream_t st) {
+    if (prec == 0)
+      hipLaunchKernelGGL((unpack_kernel<Model, Fp64>), dim3(grid(count)), dim3(kAuxBlock), 0, st,
+                         state, stride, first, count, dst, ld);
+    else
+      hipLaunchKernelGGL((unpack_kernel<Model, Mixed>), dim3(grid(count)), dim3(kAuxBlock), 0, st,
+                         state, stride, first, count, dst, ld);
+    return hipGetLastError();
+  }
+  static hipError_t steady(int prec, const void* params, void* state, long long stride,
+                           long long n, hipStream_t st) {
+    if (prec == 0)
+      hipLaunchKernelGGL((steady_gates_kernel<Model, Fp64>), dim3(grid(n)), dim3(kAuxBlock), 0, st,
+                         *static_cast<const typename Model::template Params<double>*>(params), state,
+                         stride, n);
+    else
+      hipLaunchKernelGGL((steady_gates_kernel<Model, Mixed>), dim3(grid(n)), dim3(kAuxBlock), 0, st,
+                         *static_cast<const typename Model::template Params<float>*>(params), state,
+                         stride, n);
+    return hipGetLastError();
+  }
+  static hipError_t debug_jac(int prec, const void* params, const void* state, long long stride,
+                              long long v, double stim, double diff, double* out, hipStream_t st) {
+    if (prec == 0)
+      hipLaunchKernelGGL((debug_jacobian_kernel<Model, Fp64>), dim3(1), dim3(64), 0, st,
+                         *static_cast<const typename Model::template Params<double>*>(params), state,
+                         stride, v, stim, diff, out);
+    else
+      hipLaunchKernelGGL((debug_jacobian_kernel<Model, Mixed>), dim3(1), dim3(64), 0, st,
+                         *static_cast<const typename Model::template Params<float>*>(params), state,
+                         stride, v, stim, diff, out);
+    return hipGetLastError();
+  }
+
+  static constexpr int n_raw() {
+    return int(sizeof(Model::PARAM_DEFAULTS) / sizeof(double));
+  }
+
+  // with_fp64 = false leaves sdc64 unset (the caller installs a launcher from
+  // another translation unit) so the double kernels are not instantiated here
+  template <bool with_fp64 = true>
+  static ModelOps make(const char* const* state_names) {
+    ModelOps o{};
+    o.n_states = Model::N;
+    o.n_fp64 = Model::N64;
+    o.n_params = Model::N_PARAMS;
+    o.param_names = Model::PARAM_NAMES;
+    o.param_defaults = Model::PARAM_DEFAULTS;
+    o.n_raw = n_raw();
+    o.state_names = state_names;
+    o.params_bytes[0] = sizeof(typename Model::template Params<double>);
+    o.params_bytes[1] = sizeof(typename Model::template Params<float>);
+    o.derive = &derive;
+    if constexpr (with_fp64) o.sdc64 = &sdc64;
+    o.sdc32 = &sdc32;
+    o.pack = &pack;
+    o.unpack = &unpack;
+    o.steady = &steady;
+    o.debug_jac = &debug_jac;
+    return o;
+  }
+};
+
+}  // namespace ionic

@@ -1,0 +1,439 @@
+// Fused reaction + SDC kernel (paper section 3.3.2, equations genODE,
+// picard_form, residual, sdc_ode, sdc), one vertex per lane.
+//
+// Per time step and vertex, entirely in registers:
+//   predictor   X_0 = X_n; for each Gauss-Lobatto sub-interval m, backward
+//               Euler Y - X_m - dtau_m F(Y) = 0 by local Newton with the exact
+//               sparse Jacobian; the lane stops when
+//               max_i |delta_i| / max(|Y_i|, scale_i) <= tol (>= 1 iteration,
+//               <= maxit); the wave runs until its last lane stops;
+//   corrections K times: F at every node, quadrature Q_m = sum_j S_mj dt F_j,
+//               then node by node r = X^{k+1}_m - X^k_{m+1} + Q_m and
+//               (I - dtau_m J(X^k_{m+1})) delta = r, X^{k+1}_{m+1} += delta
+//               (the linearised correction of equation sdc, generalised from
+//               the trapezoid to M nodes);
+//   X_{n+1} = X_{M-1}.
+// The time loop runs inside the kernel, so HBM sees one read and one write of
+// the state per launch.  The stimulus is constant over a step and applied iff
+// t_on <= t0 + (n + 1/2) dt < t_off.
+//
+// Precision policies: Fp64 evaluates F, J and the solve in double.  Mixed
+// evaluates them in float and keeps the first N64 states (V and the
+// intracellular concentrations), the residuals and the quadrature in double;
+// the other states are stored and updated in float.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dual.h"
+#include "sparse_solve.h"
+
+namespace ionic {
+
+constexpr int kMaxNodes = 5;
+constexpr int kMaxBatch = 24;
+constexpr int kBlock = 64;  // one wavefront per workgroup
+
+struct DevStats {
+  unsigned long long vertex_steps;
+  unsigned long long newton_iters;
+  unsigned long long newton_solves;
+  unsigned long long nonconverged;
+  unsigned long long nonfinite;
+  unsigned int it_max;
+  unsigned int pad;
+};
+
+struct SimDesc {
+  void* state;             // SoA planes
+  long long n;             // vertices
+  long long stride;        // elements per plane
+  const double* i_stim;    // amplitude per vertex or null
+  const double* i_diff;    // fixed diffusion current per vertex or null
+  double t0, dt, t_on, t_off;
+  long long step_offset;   // steps already taken from t0
+  int n_steps, n_sweeps;
+  DevStats* stats;
+  int first_block;         // first workgroup of this simulation in the launch
+  int pad;
+};
+
+template <class P>
+struct LaunchArgs {
+  P params;
+  double S[kMaxNodes - 1][kMaxNodes];  // integration matrix on the unit interval
+  double dc[kMaxNodes - 1];            // node spacing on the unit interval
+  double tol;
+  int maxit;
+  int n_sims;
+  SimDesc sims[kMaxBatch];
+};
+
+struct Fp64 {
+  using TE = double;
+  static constexpr bool mixed = false;
+};
+struct Mixed {
+  using TE = float;
+  static constexpr bool mixed = true;
+};
+
+// ---- sinks receiving the model's rows --------------------------------------------
+template <class Model, class T>
+struct SinkF {
+  T* f;
+  template <int i, uint32_t M>
+  IONIC_DEV void put(const D<T, M>& x) {
+    static_assert((M & ~Model::ROW[i]) == 0, "F_i depends on a state outside its declared row");
+    f[i] = x.v;
+  }
+};
+
+// F and A = I - dtau J on the declared pattern
+template <class Model, class T>
+struct SinkFJ {
+  T* f;
+  T (*a)[Model::N];
+  T dtau;
+  template <int i, uint32_t M>
+  IONIC_DEV void put(const D<T, M>& x) {
+    static_assert((M & ~Model::ROW[i]) == 0, "J_i has an entry outside its declared row");
+    f[i] = x.v;
+    for_bits<Model::ROW[i] | (1u << i)>([&](auto K) {
+      constexpr int k = K;
+      T jik = T(0);
+      if constexpr (has(M, k)) jik = x.template d<k>();
+      a[i][k] = (k == i ? T(1) : T(0)) - dtau * jik;
+    });
+  }
+};
+
+// dense F and J (debug entry point)
+template <class Model, class T>
+struct SinkDense {
+  T* f;
+  T* J;
+  template <int i, uint32_t M>
+  IONIC_DEV void put(const D<T, M>& x) {
+    f[i] = x.v;
+    for_bits<M>([&](auto K) {
+      constexpr int k = K;
+      J[i * Model::N + k] = x.template d<k>();
+    });
+  }
+};
+
+template <class Model, class Prec>
+struct Layout {
+  using TE = typename Prec::TE;
+  static constexpr int N = Model::N;
+  static constexpr int N64 = Prec::mixed ? Model::N64 : N;  // states held in double
+  static constexpr int N32 = N - N64;
+
+  struct Node {
+    double x64[N64];
+    float x32[N32 > 0 ? N32 : 1];
+  };
+  template <int i>
+  IONIC_DEV static auto& at(Node& n) {
+    if constexpr (i < N64)
+      return n.x64[i];
+    else
+      return n.x32[i - N64];
+  }
+  template <int i>
+  IONIC_DEV static const auto& at(const Node& n) {
+    if constexpr (i < N64)
+      return n.x64[i];
+    else
+      return n.x32[i - N64];
+  }
+
+  IONIC_DEV static void load(Node& x, const void* base, long long stride, long long v) {
+    const double* p64 = static_cast<const double*>(base);
+    const float* p32 = reinterpret_cast<const float*>(p64 + N64 * stride);
+    static_for<N>([&](auto I) {
+      constexpr int i = I;
+      if constexpr (i < N64)
+        at<i>(x) = p64[i * stride + v];
+      else
+        at<i>(x) = p32[(i - N64) * stride + v];
+    });
+  }
+  IONIC_DEV static void store(const Node& x, void* base, long long stride, long long v) {
+    double* p64 = static_cast<double*>(base);
+    float* p32 = reinterpret_cast<float*>(p64 + N64 * stride);
+    static_for<N>([&](auto I) {
+      constexpr int i = I;
+      if constexpr (i < N64)
+        p64[i * stride + v] = at<i>(x);
+      else
+        p32[(i - N64) * stride + v] = at<i>(x);
+    });
+  }
+  IONIC_DEV static void to_eval(const Node& x, TE (&xe)[N]) {
+    static_for<N>([&](auto I) {
+      constexpr int i = I;
+      xe[i] = TE(at<i>(x));
+    });
+  }
+};
+
+template <class Model, class T, class Sink, size_t... I>
+IONIC_DEV void call_rhs_F(const typename Model::template Params<T>& p, T stim, T diff, Sink& s,
+                          const T (&x)[Model::N], std::index_sequence<I...>) {
+  Model::rhs(p, stim, diff, s, plain(x[I])...);
+}
+template <class Model, class T, class Sink, size_t... I>
+IONIC_DEV void call_rhs_FJ(const typename Model::template Params<T>& p, T stim, T diff, Sink& s,
+                           const T (&x)[Model::N], std::index_sequence<I...>) {
+  Model::rhs(p, stim, diff, s, seed<T, int(I)>(x[I])...);
+}
+
+template <class Model, class T>
+IONIC_DEV void eval_F(const typename Model::template Params<T>& p, T stim, T diff,
+                      const T (&x)[Model::N], T (&f)[Model::N]) {
+  SinkF<Model, T> s{f};
+  call_rhs_F<Model, T>(p, stim, diff, s, x, std::make_index_sequence<Model::N>{});
+}
+template <class Model, class T>
+IONIC_DEV void eval_FJ(const typename Model::template Params<T>& p, T stim, T diff, T dtau,
+                       const T (&x)[Model::N], T (&f)[Model::N], T (&a)[Model::N][Model::N]) {
+  SinkFJ<Model, T> s{f, a, dtau};
+  call_rhs_FJ<Model, T>(p, stim, diff, s, x, std::make_index_sequence<Model::N>{});
+  zero_fill<Model, T>(a);
+}
+
+IONIC_DEV unsigned long long wave_sum(unsigned long long x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+IONIC_DEV unsigned int wave_max(unsigned int x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned int y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+template <class Model, class Prec, int M>
+__global__ void __launch_bounds__(kBlock)
+    sdc_kernel(const LaunchArgs<typename Model::template Params<typename Prec::TE>> args) {
+  using L = Layout<Model, Prec>;
+  using TE = typename Prec::TE;
+  using Node = typename L::Node;
+  constexpr int N = Model::N;
+
+  // which simulation this workgroup belongs to (uniform)
+  int sidx = 0;
+  for (int k = 1; k < args.n_sims; ++k)
+    if (int(blockIdx.x) >= args.sims[k].first_block) sidx = k;
+  const SimDesc& sd = args.sims[sidx];
+  const long long v = (long long)(blockIdx.x - sd.first_block) * kBlock + threadIdx.x;
+  const bool active = v < sd.n;
+  const long long vi = active ? v : sd.n - 1;  // tail lanes shadow the last vertex
+
+  const auto& p = args.params;
+  const TE stim_amp = sd.i_stim ? TE(sd.i_stim[vi]) : TE(0);
+  const TE diff = sd.i_diff ? TE(sd.i_diff[vi]) : TE(0);
+  const double dt = sd.dt;
+  TE dtau[M - 1];
+  double Sdt[M - 1][M];
+  static_for<M - 1>([&](auto m) {
+    dtau[m] = TE(args.dc[m] * dt);
+    static_for<M>([&](auto j) { Sdt[m][j] = args.S[m][j] * dt; });
+  });
+  const TE tol = TE(args.tol);
+
+  Node X[M];
+  L::load(X[0], sd.state, sd.stride, vi);
+
+  unsigned long long it_total = 0;
+  unsigned int it_max = 0, nonconv = 0;
+
+  for (int step = 0; step < sd.n_steps; ++step) {
+    const double t_mid = sd.t0 + (double(sd.step_offset + step) + 0.5) * dt;
+    const TE stim = (sd.t_on <= t_mid && t_mid < sd.t_off) ? stim_amp : TE(0);
+
+    // ---- predictor: backward Euler by local Newton on each sub-interval
+    static_for<M - 1>([&](auto MM) {
+      constexpr int m = MM;
+      Node Y = X[m];
+      int it = 0;
+      bool conv = false;
+      do {
+        TE xe[N], f[N], a[N][N], b[N];
+        L::to_eval(Y, xe);
+        eval_FJ<Model, TE>(p, stim, diff, dtau[m], xe, f, a);
+        static_for<N>([&](auto I) {
+          constexpr int i = I;
+          const double g = double(L::template at<i>(Y)) - double(L::template at<i>(X[m])) -
+                           double(dtau[m]) * double(f[i]);
+          b[i] = TE(-g);
+        });
+        sparse_solve<Model, TE>(a, b);
+        TE err = TE(0);
+        static_for<N>([&](auto I) {
+          constexpr int i = I;
+          auto& y = L::template at<i>(Y);
+          y += b[i];
+          const TE ay = fabs(TE(y));
+          const TE s = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
+          const TE e = fabs(b[i]) / s;
+          err = e > err ? e : err;
+        });
+        ++it;
+        conv = err <= tol;
+      } while (!conv && it < args.maxit);
+      X[m + 1] = Y;
+      it_total += (unsigned long long)it;
+      it_max = (unsigned int)it > it_max ? (unsigned int)it : it_max;
+      nonconv += conv ? 0u : 1u;
+    });
+
+    // ---- corrections
+    if (sd.n_sweeps > 0) {
+      TE F0[N];
+      {
+        TE xe[N];
+        L::to_eval(X[0], xe);
+        eval_F<Model, TE>(p, stim, diff, xe, F0);
+      }
+      for (int k = 0; k < sd.n_sweeps; ++k) {
+        double Q[M - 1][N];
+        static_for<M - 1>([&](auto m) {
+          static_for<N>([&](auto i) { Q[m][i] = Sdt[m][0] * double(F0[i]); });
+        });
+        // F at nodes 2..M-1 (node 1 comes with its Jacobian below)
+        static_for<M - 2>([&](auto JJ) {
+          constexpr int jn = JJ + 2;
+          TE xe[N], fj[N];
+          L::to_eval(X[jn], xe);
+          eval_F<Model, TE>(p, stim, diff, xe, fj);
+          static_for<M - 1>([&](auto m) {
+            static_for<N>([&](auto i) { Q[m][i] += Sdt[m][jn] * double(fj[i]); });
+          });
+        });
+        static_for<M - 1>([&](auto MM) {
+          constexpr int m = MM;
+          TE xe[N], f[N], a[N][N], b[N];
+          L::to_eval(X[m + 1], xe);
+          eval_FJ<Model, TE>(p, stim, diff, dtau[m], xe, f, a);
+          if constexpr (m == 0) {
+            static_for<M - 1>([&](auto mm) {
+              static_for<N>([&](auto i) { Q[mm][i] += Sdt[mm][1] * double(f[i]); });
+            });
+          }
+          static_for<N>([&](auto I) {
+            constexpr int i = I;
+            const double r = double(L::template at<i>(X[m])) - double(L::template at<i>(X[m + 1])) +
+                             Q[m][i];
+            b[i] = TE(r);
+          });
+          sparse_solve<Model, TE>(a, b);
+          static_for<N>([&](auto I) {
+            constexpr int i = I;
+            L::template at<i>(X[m + 1]) += b[i];
+          });
+        });
+      }
+    }
+    X[0] = X[M - 1];
+  }
+
+  unsigned int nonfinite = 0;
+  static_for<N>([&](auto I) {
+    constexpr int i = I;
+    if (!isfinite(double(L::template at<i>(X[0])))) nonfinite = 1;
+  });
+  if (active) L::store(X[0], sd.state, sd.stride, v);
+
+  // wave-level reduction of the statistics, one set of atomics per wave
+  const unsigned long long a_iters = wave_sum(active ? it_total : 0ull);
+  const unsigned long long a_nonconv = wave_sum(active ? nonconv : 0u);
+  const unsigned long long a_nonfin = wave_sum(active ? nonfinite : 0u);
+  const unsigned long long a_act = wave_sum(active ? 1ull : 0ull);
+  const unsigned int a_itmax = wave_max(active ? it_max : 0u);
+  if (threadIdx.x == 0 && sd.stats) {
+    atomicAdd(&sd.stats->vertex_steps, a_act * (unsigned long long)sd.n_steps);
+    atomicAdd(&sd.stats->newton_iters, a_iters);
+    atomicAdd(&sd.stats->newton_solves, a_act * (unsigned long long)sd.n_steps * (M - 1));
+    atomicAdd(&sd.stats->nonconverged, a_nonconv);
+    atomicAdd(&sd.stats->nonfinite, a_nonfin);
+    atomicMax(&sd.stats->it_max, a_itmax);
+  }
+}
+
+// ---- auxiliary kernels --------------------------------------------------------------
+
+// FP64 SoA rows (n_states x count, row stride ld) -> precision layout at [first, first+count)
+template <class Model, class Prec>
+__global__ void pack_kernel(const double* __restrict__ src, long long ld, void* state,
+                            long long stride, long long first, long long count) {
+  using L = Layout<Model, Prec>;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  typename L::Node x;
+  static_for<Model::N>([&](auto I) {
+    constexpr int i = I;
+    L::template at<i>(x) = src[i * ld + t];
+  });
+  L::store(x, state, stride, first + t);
+}
+
+// precision layout -> FP64 SoA rows
+template <class Model, class Prec>
+__global__ void unpack_kernel(const void* state, long long stride, long long first,
+                              long long count, double* __restrict__ dst, long long ld) {
+  using L = Layout<Model, Prec>;
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= count) return;
+  typename L::Node x;
+  L::load(x, state, stride, first + t);
+  static_for<Model::N>([&](auto I) {
+    constexpr int i = I;
+    dst[i * ld + t] = double(L::template at<i>(x));
+  });
+}
+
+template <class Model, class Prec>
+__global__ void steady_gates_kernel(const typename Model::template Params<typename Prec::TE> p,
+                                    void* state, long long stride, long long n) {
+  using L = Layout<Model, Prec>;
+  using TE = typename Prec::TE;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  typename L::Node x;
+  L::load(x, state, stride, v);
+  TE xe[Model::N];
+  L::to_eval(x, xe);
+  Model::template steady_gates<TE>(p, xe);
+  static_for<Model::N>([&](auto I) {
+    constexpr int i = I;
+    if constexpr (i >= Model::N64) L::template at<i>(x) = xe[i];
+  });
+  L::store(x, state, stride, v);
+}
+
+template <class Model, class Prec>
+__global__ void debug_jacobian_kernel(const typename Model::template Params<typename Prec::TE> p,
+                                      const void* state, long long stride, long long v,
+                                      double stim, double diff, double* out /* N + N*N */) {
+  using L = Layout<Model, Prec>;
+  using TE = typename Prec::TE;
+  constexpr int N = Model::N;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  typename L::Node x;
+  L::load(x, state, stride, v);
+  TE xe[N], f[N], J[N * N];
+  for (int k = 0; k < N * N; ++k) J[k] = TE(0);
+  L::to_eval(x, xe);
+  SinkDense<Model, TE> s{f, J};
+  call_rhs_FJ<Model, TE>(p, TE(stim), TE(diff), s, xe, std::make_index_sequence<N>{});
+  for (int i = 0; i < N; ++i) out[i] = double(f[i]);
+  for (int k = 0; k < N * N; ++k) out[N + k] = double(J[k]);
+}
+
+}  // namespace ionic

@@ -1,0 +1,302 @@
+"""ctypes binding of libionic_sdc.so (the C ABI in include/ionic_sdc.h).
+
+Argument marshalling only: every step of the reaction + SDC stage runs in the
+library's HIP kernels.  The functions below carry the C entry points' names
+and raise IonicError on a non-zero status.  PyTorch provides device memory
+(uint8 tensors for the state, float64 tensors for inputs) and streams.  The
+library must be built (``__graft_entry__.build()``); without it every call
+fails loudly -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_size_t, c_void_p
+
+import numpy as np
+
+LR91, TT06_EPI, TEST_LINEAR, TEST_LOGISTIC = 1, 2, 90, 91
+FP64, MIXED = 0, 1
+MODEL_IDS = {"LR91": LR91, "TT06": TT06_EPI, "TEST_LINEAR": TEST_LINEAR, "TEST_LOGISTIC": TEST_LOGISTIC}
+PRECISIONS = {"fp64": FP64, "mixed": MIXED}
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_lib", "libionic_sdc.so")
+
+
+class IonicError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("ionic status %d: %s" % (status, message))
+        self.status = status
+
+
+class ionic_config(ctypes.Structure):
+    _fields_ = [
+        ("n_vertices", c_int64),
+        ("model", c_int32),
+        ("precision", c_int32),
+        ("newton_tol", c_double),
+        ("newton_maxit", c_int32),
+        ("n_params", c_int32),
+        ("params", POINTER(c_double)),
+    ]
+
+
+class ionic_stats(ctypes.Structure):
+    _fields_ = [
+        ("vertex_steps", c_int64),
+        ("newton_iters", c_int64),
+        ("newton_solves", c_int64),
+        ("n_nonconverged", c_int64),
+        ("n_nonfinite", c_int64),
+        ("newton_it_max", c_int32),
+        ("reserved", c_int32),
+    ]
+
+
+_SIGNATURES = {
+    "ionic_n_states": (c_int, [c_int]),
+    "ionic_n_fp64_states": (c_int, [c_int]),
+    "ionic_state_name": (ctypes.c_char_p, [c_int, c_int]),
+    "ionic_n_params": (c_int, [c_int]),
+    "ionic_param_name": (ctypes.c_char_p, [c_int, c_int]),
+    "ionic_plane_stride": (c_int64, [c_int64]),
+    "ionic_state_bytes": (c_size_t, [c_int, c_int, c_int64]),
+    "ionic_lobatto": (c_int, [c_int, POINTER(c_double), POINTER(c_double)]),
+    "ionic_init": (c_int, [POINTER(c_void_p), POINTER(ionic_config), c_void_p, c_size_t,
+                           c_void_p, c_int, c_void_p]),
+    "ionic_destroy": (None, [c_void_p]),
+    "reaction_sdc_step": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_int, c_void_p,
+                                  c_double, c_double, c_void_p, c_void_p]),
+    "ionic_set_inputs": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_void_p, c_double,
+                                 c_double, c_void_p]),
+    "reaction_sdc_step_batch": (c_int, [POINTER(c_void_p), POINTER(c_int), c_int, c_void_p]),
+    "state_readback": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int, c_void_p]),
+    "ionic_gates_to_steady_state": (c_int, [c_void_p, c_void_p]),
+    "ionic_get_stats": (c_int, [c_void_p, POINTER(ionic_stats)]),
+    "ionic_reset_stats": (c_int, [c_void_p]),
+    "ionic_debug_jacobian": (c_int, [c_void_p, c_int64, c_double, c_double, POINTER(c_double),
+                                     POINTER(c_double), c_void_p]),
+    "ionic_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the library (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("%s is missing: build it with __graft_entry__.build()" % LIB_PATH)
+        handle = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGNATURES.items():
+            fn = getattr(handle, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = handle
+    return _lib
+
+
+def _check(status):
+    if status != 0:
+        raise IonicError(status, lib().ionic_last_error().decode())
+    return status
+
+
+def _ptr(x):
+    """Device/host address of a torch tensor, an int address, or None."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    return x.data_ptr()
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ---- entry points with the C names -------------------------------------------------
+def ionic_n_states(model):
+    n = lib().ionic_n_states(model)
+    if n < 0:
+        _check(n)
+    return n
+
+
+def ionic_n_fp64_states(model):
+    n = lib().ionic_n_fp64_states(model)
+    if n < 0:
+        _check(n)
+    return n
+
+
+def ionic_state_name(model, idx):
+    s = lib().ionic_state_name(model, idx)
+    return None if s is None else s.decode()
+
+
+def ionic_n_params(model):
+    n = lib().ionic_n_params(model)
+    if n < 0:
+        _check(n)
+    return n
+
+
+def ionic_param_name(model, idx):
+    s = lib().ionic_param_name(model, idx)
+    return None if s is None else s.decode()
+
+
+def ionic_plane_stride(n):
+    return lib().ionic_plane_stride(n)
+
+
+def ionic_state_bytes(model, precision, n):
+    return lib().ionic_state_bytes(model, precision, n)
+
+
+def ionic_lobatto(n_nodes):
+    c = (c_double * n_nodes)()
+    S = (c_double * ((n_nodes - 1) * n_nodes))()
+    _check(lib().ionic_lobatto(n_nodes, c, S))
+    return np.array(c[:]), np.array(S[:]).reshape(n_nodes - 1, n_nodes)
+
+
+def make_config(model, n_vertices, precision=FP64, newton_tol=1e-10, newton_maxit=10, params=None):
+    cfg = ionic_config()
+    cfg.n_vertices = int(n_vertices)
+    cfg.model = int(model)
+    cfg.precision = int(precision)
+    cfg.newton_tol = float(newton_tol)
+    cfg.newton_maxit = int(newton_maxit)
+    if params is not None and len(params) > 0:
+        arr = (c_double * len(params))(*[float(p) for p in params])
+        cfg.n_params = len(params)
+        cfg.params = ctypes.cast(arr, POINTER(c_double))
+        cfg._keep = arr
+    else:
+        cfg.n_params = 0
+        cfg.params = None
+    return cfg
+
+
+def ionic_init(cfg, state_ptr, state_bytes, x0, x0_on_device=False, stream=None):
+    """Returns the opaque handle (an int).  x0: host numpy (n, N) float64 or a device address."""
+    h = c_void_p()
+    if x0_on_device:
+        x0p = _ptr(x0)
+        keep = None
+    else:
+        keep = np.ascontiguousarray(x0, dtype=np.float64)
+        x0p = keep.ctypes.data
+    _check(lib().ionic_init(ctypes.byref(h), ctypes.byref(cfg), state_ptr, state_bytes, x0p,
+                            1 if x0_on_device else 0, _stream(stream)))
+    del keep
+    return h.value
+
+
+def ionic_destroy(handle):
+    lib().ionic_destroy(handle)
+
+
+def reaction_sdc_step(handle, t0, dt, n_steps, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0,
+                      stim_t_off=0.0, i_diff=None, stream=None):
+    _check(lib().reaction_sdc_step(handle, t0, dt, n_steps, n_nodes, n_sweeps, _ptr(i_stim),
+                                   stim_t_on, stim_t_off, _ptr(i_diff), _stream(stream)))
+
+
+def ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0,
+                     stim_t_off=0.0, i_diff=None):
+    _check(lib().ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, _ptr(i_stim), stim_t_on,
+                                  stim_t_off, _ptr(i_diff)))
+
+
+def reaction_sdc_step_batch(handles, n_steps, stream=None):
+    n = len(handles)
+    hs = (c_void_p * n)(*handles)
+    ns = (c_int * n)(*[int(k) for k in n_steps])
+    _check(lib().reaction_sdc_step_batch(hs, ns, n, _stream(stream)))
+
+
+def state_readback(handle, n_states, first, count, out=None, stream=None):
+    """Returns a host (n_states, count) float64 array, or fills a device tensor `out`."""
+    if out is not None:
+        _check(lib().state_readback(handle, _ptr(out), first, count, 1, _stream(stream)))
+        return out
+    host = np.empty((n_states, count), dtype=np.float64)
+    _check(lib().state_readback(handle, host.ctypes.data, first, count, 0, _stream(stream)))
+    return host
+
+
+def ionic_gates_to_steady_state(handle, stream=None):
+    _check(lib().ionic_gates_to_steady_state(handle, _stream(stream)))
+
+
+def ionic_get_stats(handle):
+    st = ionic_stats()
+    _check(lib().ionic_get_stats(handle, ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in ionic_stats._fields_ if name != "reserved"}
+
+
+def ionic_reset_stats(handle):
+    _check(lib().ionic_reset_stats(handle))
+
+
+def ionic_debug_jacobian(handle, n_states, vertex, i_stim=0.0, i_diff=0.0, stream=None):
+    F = (c_double * n_states)()
+    J = (c_double * (n_states * n_states))()
+    _check(lib().ionic_debug_jacobian(handle, vertex, i_stim, i_diff, F, J, _stream(stream)))
+    return np.array(F[:]), np.array(J[:]).reshape(n_states, n_states)
+
+
+# ---- convenience wrapper ----------------------------------------------------------------
+class Simulation:
+    """One simulation: a device state buffer (torch uint8 tensor) plus its handle."""
+
+    def __init__(self, model, x0, precision=FP64, newton_tol=1e-10, newton_maxit=10, params=None,
+                 stream=None, device="cuda"):
+        import torch
+        model = MODEL_IDS.get(model, model)
+        precision = PRECISIONS.get(precision, precision)
+        x0 = np.asarray(x0, dtype=np.float64)
+        self.model, self.precision = model, precision
+        self.n_states = ionic_n_states(model)
+        if x0.ndim != 2 or x0.shape[0] != self.n_states:
+            raise ValueError("x0 must have shape (%d, N)" % self.n_states)
+        self.n = x0.shape[1]
+        nbytes = ionic_state_bytes(model, precision, self.n)
+        self.state = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.config = make_config(model, self.n, precision, newton_tol, newton_maxit, params)
+        self.handle = ionic_init(self.config, self.state.data_ptr(), nbytes, x0, False, stream)
+
+    def step(self, t0, dt, n_steps, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0, stim_t_off=0.0,
+             i_diff=None, stream=None):
+        reaction_sdc_step(self.handle, t0, dt, n_steps, n_nodes, n_sweeps, i_stim, stim_t_on,
+                          stim_t_off, i_diff, stream)
+
+    def readback(self, first=0, count=None, stream=None):
+        count = self.n - first if count is None else count
+        return state_readback(self.handle, self.n_states, first, count, stream=stream)
+
+    def stats(self):
+        return ionic_get_stats(self.handle)
+
+    def debug_jacobian(self, vertex, i_stim=0.0, i_diff=0.0):
+        return ionic_debug_jacobian(self.handle, self.n_states, vertex, i_stim, i_diff)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            ionic_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

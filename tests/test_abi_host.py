@@ -1,0 +1,122 @@
+"""Host-only checks of the C-ABI library (no GPU needed): it loads, exports
+every function include/ionic_sdc.h declares, its enum values match the
+binding, its own Gauss-Lobatto nodes and integration matrix match the closed
+forms (paper section 3.3.2: two nodes = the trapezoid of equation sdc), and
+invalid arguments are rejected with the documented codes before any HIP call.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2510_27447_amd import ionic as I
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include",
+                      "ionic_sdc.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_library_exports_every_declared_function():
+    lib = I.lib()
+    names = declared_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding wraps every one of them
+    assert set(names) <= set(I._SIGNATURES)
+
+
+def test_enum_values_match_header():
+    text = open(HEADER).read()
+    for name, val in [("IONIC_LR91", I.LR91), ("IONIC_TT06_EPI", I.TT06_EPI),
+                      ("IONIC_TEST_LINEAR", I.TEST_LINEAR), ("IONIC_TEST_LOGISTIC", I.TEST_LOGISTIC),
+                      ("IONIC_FP64", I.FP64), ("IONIC_MIXED", I.MIXED)]:
+        assert re.search(r"\b%s\s*=\s*%d\b" % (name, val), text), name
+
+
+def test_model_description():
+    assert I.ionic_n_states(I.LR91) == 8
+    assert I.ionic_n_states(I.TT06_EPI) == 19
+    assert I.ionic_n_fp64_states(I.LR91) == 2
+    assert I.ionic_n_fp64_states(I.TT06_EPI) == 6
+    assert [I.ionic_state_name(I.TT06_EPI, i) for i in range(6)] == ["V", "Cai", "CaSR", "CaSS", "Nai", "Ki"]
+    assert I.ionic_state_name(I.LR91, 8) is None
+    assert I.ionic_param_name(I.LR91, 0) == "G_Na"
+    with pytest.raises(I.IonicError):
+        I.ionic_n_states(5)
+
+
+def test_state_bytes():
+    assert I.ionic_plane_stride(1) == 64
+    assert I.ionic_plane_stride(64) == 64
+    assert I.ionic_plane_stride(65) == 128
+    n = 1_000_000
+    assert I.ionic_state_bytes(I.TT06_EPI, I.FP64, n) == 19 * n * 8
+    assert I.ionic_state_bytes(I.TT06_EPI, I.MIXED, n) == 6 * n * 8 + 13 * n * 4
+    assert I.ionic_state_bytes(I.LR91, I.MIXED, 100) == 128 * (2 * 8 + 6 * 4)
+    assert I.ionic_state_bytes(7, I.FP64, 10) == 0
+    assert I.ionic_state_bytes(I.LR91, 3, 10) == 0
+    assert I.ionic_state_bytes(I.LR91, I.FP64, 0) == 0
+
+
+def test_library_quadrature_closed_forms():
+    s5, s21 = np.sqrt(5.0), np.sqrt(21.0)
+    expect = {2: [0, 1], 3: [0, .5, 1], 4: [0, (5 - s5) / 10, (5 + s5) / 10, 1],
+              5: [0, (7 - s21) / 14, .5, (7 + s21) / 14, 1]}
+    for M, cs in expect.items():
+        c, S = I.ionic_lobatto(M)
+        np.testing.assert_allclose(c, cs, atol=1e-15)
+        np.testing.assert_allclose(S.sum(1), np.diff(cs), atol=1e-15)
+        for deg in range(M):
+            np.testing.assert_allclose(S @ (c ** deg), np.diff(c ** (deg + 1)) / (deg + 1), atol=1e-15)
+    np.testing.assert_allclose(I.ionic_lobatto(2)[1], [[0.5, 0.5]], atol=0)
+    np.testing.assert_allclose(I.ionic_lobatto(3)[1], [[5 / 24, 1 / 3, -1 / 24], [-1 / 24, 1 / 3, 5 / 24]],
+                               atol=1e-16)
+    with pytest.raises(I.IonicError):
+        I.ionic_lobatto(6)
+
+
+def _init_status(cfg, state=0x1000, nbytes=1 << 30, x0=True):
+    import ctypes
+    h = ctypes.c_void_p()
+    arr = np.zeros((8, 10))
+    return I.lib().ionic_init(ctypes.byref(h), ctypes.byref(cfg) if cfg is not None else None,
+                              state, nbytes, arr.ctypes.data if x0 else None, 0, None)
+
+
+def test_init_rejects_bad_arguments_before_any_hip_call():
+    good = I.make_config(I.LR91, 10)
+    assert _init_status(None) == -1
+    assert _init_status(I.make_config(7, 10)) == -2
+    assert _init_status(I.make_config(I.LR91, 10, precision=4)) == -2
+    assert _init_status(I.make_config(I.LR91, 0)) == -1
+    assert _init_status(I.make_config(I.LR91, 10, newton_tol=-1.0)) == -1
+    assert _init_status(I.make_config(I.LR91, 10, newton_tol=float("nan"))) == -1
+    assert _init_status(I.make_config(I.LR91, 10, newton_maxit=0)) == -1
+    assert _init_status(I.make_config(I.LR91, 10, newton_maxit=65)) == -1
+    assert _init_status(I.make_config(I.LR91, 10, params=[1.0] * 16)) == -1
+    assert _init_status(good, state=0) == -1
+    assert _init_status(good, nbytes=10) == -1
+    assert _init_status(good, x0=False) == -1
+    assert "x0" in I.lib().ionic_last_error().decode()
+
+
+def test_step_entry_points_reject_bad_arguments():
+    lib = I.lib()
+    assert lib.reaction_sdc_step(None, 0.0, 0.02, 1, 3, 2, None, 0, 0, None, None) == -1
+    assert lib.ionic_set_inputs(None, 0.0, 0.02, 3, 2, None, 0, 0, None) == -1
+    assert lib.state_readback(None, None, 0, 1, 0, None) == -1
+    assert lib.ionic_get_stats(None, None) == -1
+    assert lib.ionic_gates_to_steady_state(None, None) == -1
+    assert lib.reaction_sdc_step_batch(None, None, 0, None) == 0
+    assert lib.reaction_sdc_step_batch(None, None, 1, None) == -1
+    assert lib.reaction_sdc_step_batch(None, None, -1, None) == -1
+    lib.ionic_destroy(None)

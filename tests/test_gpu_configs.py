@@ -1,0 +1,80 @@
+"""GPU vs oracle at the full sizes of the benchmark configurations, in the
+launch configuration the benchmark times (one fused launch over all vertices
+and all steps).  The oracle computes a seeded sample of vertices one by one
+(vertices are independent in the reaction stage, so the sample's values are
+exactly what the full run produces for them): stimulated vertices, the ragged
+tail and random interior ones.
+
+C1 LR91 fp64 (4096 vertices, 1000 steps), C2 TT06 fp64 (100^3, 500 steps),
+C3 the same in mixed precision (<= 1e-4 against the fp64 oracle, max and RMS
+reported for V and every concentration), C4 TT06 spiral (200^3, 1000 steps,
+4 nodes, diffusion input redrawn every 50 steps) in both precisions."""
+import numpy as np
+import pytest
+
+from gpu_helpers import rel_errors, run_gpu, run_oracle, say
+from paper_2510_27447_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+_ORACLE = {}
+
+
+def sample(w, n_stim, n_rand, seed=7):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    idx = set()
+    if w.i_stim is not None:
+        st = np.nonzero(w.i_stim != 0)[0]
+        idx |= set(rng.choice(st, size=min(n_stim, len(st)), replace=False).tolist())
+    idx |= set(rng.choice(w.n, size=n_rand, replace=False).tolist())
+    idx |= {0, w.n - 1}
+    return np.array(sorted(idx))
+
+
+def oracle_on(w, idx, key):
+    if key not in _ORACLE:
+        _ORACLE[key] = run_oracle(w.subset(idx))
+    return _ORACLE[key]
+
+
+def check(w, idx, key, tol_v, tol_conc, n64):
+    say("case", w.name, "N", w.n, "sample", len(idx))
+    Xg, st = run_gpu(w)
+    say("  stats", st)
+    Xo = oracle_on(w, idx, key)
+    err = rel_errors(Xg[:, idx], Xo, list(range(w.x0.shape[0])))
+    say("  V max %.3e rms %.3e" % err[0], " fp64-held:", ["%.2e" % err[i][0] for i in range(n64)])
+    assert st["n_nonfinite"] == 0
+    assert st["vertex_steps"] == w.n * w.n_steps
+    assert err[0][0] <= tol_v
+    for i in range(1, n64):
+        assert err[i][0] <= tol_conc, i
+    return err
+
+
+def test_c1_lr91_fp64():
+    w = W.c1_lr91()
+    idx = sample(w, 48, 80)
+    check(w, idx, "c1", 1e-10, 1e-9, 2)
+
+
+def test_c2_tt06_fp64():
+    w = W.c2_tt06()
+    idx = sample(w, 16, 32)
+    check(w, idx, "c2", 1e-10, 1e-9, 6)
+
+
+def test_c3_tt06_mixed():
+    w = W.c3_tt06_mixed()
+    idx = sample(w, 16, 32)
+    err = check(w, idx, "c2", 1e-4, 1e-4, 6)   # against the fp64 oracle of C2
+    say("  C3 error vs fp64 oracle (max, rms):", {k: err[k] for k in range(6)})
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c4_tt06_spiral(precision):
+    w = W.c4_tt06_spiral(precision=precision)
+    rng = np.random.Generator(np.random.PCG64(3))
+    idx = np.array(sorted(set(rng.choice(w.n, 14, replace=False).tolist()) | {0, w.n - 1}))
+    tol = 1e-10 if precision == "fp64" else 1e-4
+    check(w, idx, "c4", tol, 100 * tol, 6)
