@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X reaction + SDC stage (one JSON line on stdout).
+
+Workload: TT06 epicardial model on a 100x100x100 slab (1,000,000 vertices),
+rest + U(-1, 1) mV, planar stimulus on the x = 0 face for 2 ms, fixed
+diffusion current N(0, 0.5^2); dt = 0.02 ms, 500 steps per launch, 3
+Gauss-Lobatto nodes, 3 sweeps, Newton tol 1e-10.  One benchmark "step" is
+one whole pass of that workload: a single fused launch advancing every vertex
+through all 500 time steps from the initial state (the state buffer is
+restored by a device copy before each pass).  Measured in mixed precision
+(the reported value) and in plain fp64 on the same GPU.
+
+Reported: vertex-steps/s over the timed passes (wall clock, inputs resident
+in HBM), kernel time from HIP events on the launch stream, the roofline
+fraction of the dominant kernel (algorithmic flops from the per-evaluation
+operation counts below and the Newton iterations the launch took), the
+mixed-vs-fp64 difference on the full field, the serving latency of the
+continuous-batching loop on the seeded request trace, and the CPU oracle
+timed on a bounded sample of the same workload.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-serving] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+# Operation counts per evaluation of the TT06 model (forward-mode
+# differentiation on the compile-time Jacobian pattern; printed by
+# `python -m oracle.opcount`, checked against it by the CPU tests).
+TT06_FLOPS = {"F": 553, "FJ": 1250, "solve": 362}
+LR91_FLOPS = {"F": 232, "FJ": 465, "solve": 75}
+PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector fp64 / fp32 (published)
+HBM_PEAK_GBS = 8000.0
+
+
+def flops_per_launch(ev, n_states, vertex_steps, M, K, newton_iters):
+    F_evals = vertex_steps * (1 + K * (M - 2)) if K > 0 else 0
+    FJ = newton_iters + vertex_steps * K * (M - 1)
+    return (F_evals * ev["F"] + FJ * (ev["FJ"] + ev["solve"]) + newton_iters * 6 * n_states
+            + vertex_steps * K * ((M - 1) * M * 2 + (M - 1) * 3) * n_states)
+
+
+def state_bytes_per_vertex(precision):
+    return 19 * 8 if precision == "fp64" else 6 * 8 + 13 * 4
+
+
+def run_pass_set(I, torch, w, steps, warmup):
+    sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
+                       newton_maxit=w.newton_maxit)
+    stim = torch.as_tensor(w.i_stim).cuda()
+    diff = torch.as_tensor(w.i_diff).cuda()
+    init = sim.state.clone()
+    stream = torch.cuda.current_stream()
+
+    def one_pass():
+        sim.state.copy_(init)
+        sim.step(0.0, w.dt, w.n_steps, w.n_nodes, w.n_sweeps, stim, w.stim_t_on, w.stim_t_off,
+                 diff, stream=stream)
+
+    for _ in range(warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    I.ionic_reset_stats(sim.handle)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        sim.state.copy_(init)
+        starts[k].record(stream)
+        sim.step(0.0, w.dt, w.n_steps, w.n_nodes, w.n_sweeps, stim, w.stim_t_on, w.stim_t_off,
+                 diff, stream=stream)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    st = sim.stats()
+    V = sim.readback()[0]
+    sim.close()
+    vsteps = w.n * w.n_steps
+    iters = st["newton_iters"] / steps
+    flops = flops_per_launch(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps, iters)
+    kavg = float(np.mean(kernel_ms)) / 1e3
+    achieved = flops / kavg / 1e12
+    bytes_launch = w.n * (2 * state_bytes_per_vertex(w.precision) + 2 * 8)  # state r/w, stim, diff
+    return {
+        "value": vsteps * steps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "kernel_ms": float(np.mean(kernel_ms)),
+        "kernel_ms_all": [round(x, 3) for x in kernel_ms],
+        "newton_iters_per_solve": st["newton_iters"] / max(1, st["newton_solves"]),
+        "newton_it_max": st["newton_it_max"],
+        "n_nonconverged": st["n_nonconverged"],
+        "n_nonfinite": st["n_nonfinite"],
+        "algorithmic_flops_per_launch": flops,
+        "roofline": {
+            "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[w.precision],
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[w.precision], 4),
+            "traffic": None,
+        },
+        "hbm_gbs_algorithmic": bytes_launch / kavg / 1e9,
+        "V": V,
+    }
+
+
+def cpu_baseline(n_vertices=1024, n_steps=50):
+    """The oracle (fp64 numpy, single thread) on a bounded sample of the workload."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.models import TT06
+    from oracle.sdc import advance
+    from paper_2510_27447_amd import workloads as W
+    w = W.c2_tt06(nx=100, ny=100, nz=100)
+    rng = np.random.Generator(np.random.PCG64(11))
+    idx = np.sort(np.concatenate([rng.choice(np.nonzero(w.i_stim)[0], 4, replace=False),
+                                  rng.choice(w.n, n_vertices - 4, replace=False)]))
+    s = w.subset(idx)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        advance(TT06, s.x0, dt=s.dt, n_steps=n_steps, n_nodes=s.n_nodes, n_sweeps=s.n_sweeps,
+                i_stim=s.i_stim, stim_on=s.stim_t_on, stim_off=s.stim_t_off, i_diff=s.i_diff,
+                tol=s.newton_tol, maxit=s.newton_maxit)
+        dt = time.perf_counter() - t0
+    return {"value": n_vertices * n_steps / dt, "unit": "vertex-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "%d vertices (4 stimulated) x %d steps of the C2 slab, fp64 numpy oracle, "
+                      "1 thread, %.1f s" % (n_vertices, n_steps, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=256)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the reaction stage shards by vertex ranges with no "
+              "exchange, and this build runs and reports a single MI355X only (--gpus 1).",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2510_27447_amd import ionic as I
+    from paper_2510_27447_amd import workloads as W
+
+    I.lib()
+    res = {}
+    for prec in ("fp64", "mixed"):
+        w = W.c2_tt06(precision=prec)
+        print("[bench] %s: %d vertices x %d steps, %d passes" % (w.name, w.n, w.n_steps, args.steps),
+              file=sys.stderr, flush=True)
+        res[prec] = run_pass_set(I, torch, w, args.steps, args.warmup)
+        print("[bench] %s: %.3e vertex-steps/s, kernel %.1f ms" % (prec, res[prec]["value"],
+              res[prec]["kernel_ms"]), file=sys.stderr, flush=True)
+    Vf, Vm = res["fp64"].pop("V"), res["mixed"].pop("V")
+    mixed_err = {"max": float(np.max(np.abs(Vm - Vf)) / np.max(np.abs(Vf))),
+                 "rms": float(np.sqrt(np.mean((Vm - Vf) ** 2)) / np.max(np.abs(Vf)))}
+
+    serving = None
+    if not args.no_serving:
+        from paper_2510_27447_amd import serve
+        print("[bench] serving trace: %d requests" % args.serving_requests, file=sys.stderr, flush=True)
+        serving = serve.run_trace(W.c5_trace(n_requests=args.serving_requests), verbose=True)
+
+    cpu = None
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
+        cpu = cpu_baseline()
+
+    m = res["mixed"]
+    out = {
+        "metric": "TT06 vertex-steps/s, mixed vs FP64 at stated error; serving p50/p99 latency",
+        "value": m["value"],
+        "unit": "vertex-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "TT06-epi 100x100x100 slab (1e6 vertices), 500 steps of dt 0.02 ms per "
+                        "pass, 3 Gauss-Lobatto nodes, 3 SDC sweeps, Newton tol 1e-10; value = "
+                        "mixed precision (fp32 F/J/solve, fp64 V/Ca/Na/K/residual); fp64 alongside",
+            "n_vertices": 1_000_000, "steps_per_pass": 500, "dt_ms": 0.02, "nodes": 3, "sweeps": 3,
+            "seed": 0,
+        },
+        "kernel_ms": m["kernel_ms"],
+        "fp64": {k: res["fp64"][k] for k in ("value", "ms_per_step", "kernel_ms", "roofline",
+                                            "newton_iters_per_solve", "n_nonconverged")},
+        "mixed_speedup_vs_fp64": m["value"] / res["fp64"]["value"],
+        "mixed_vs_fp64_V_error": mixed_err,
+        "newton_iters_per_solve": m["newton_iters_per_solve"],
+        "roofline": m["roofline"],
+        "hbm_gbs_algorithmic": m["hbm_gbs_algorithmic"],
+        "cpu_baseline": cpu,
+        "serving": serving,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

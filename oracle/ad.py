@@ -74,6 +74,30 @@ class Dual:
         vp = self.v ** p
         return Dual(vp, self.d * (p * self.v ** (p - 1)))
 
+    # elementary functions (dispatched from the module functions below)
+    def _exp(self):
+        e = np.exp(self.v)
+        return Dual(e, self.d * e)
+
+    def _expm1(self):
+        return Dual(np.expm1(self.v), self.d * np.exp(self.v))
+
+    def _log(self):
+        return Dual(np.log(self.v), self.d / self.v)
+
+    def _sqrt(self):
+        s = np.sqrt(self.v)
+        return Dual(s, self.d * (0.5 / s))
+
+    @staticmethod
+    def _where(cond, a, b):
+        shape_n = (a.d if isinstance(a, Dual) else b.d).shape
+        av = val(a)
+        bv = val(b)
+        ad = a.d if isinstance(a, Dual) else np.zeros(shape_n)
+        bd = b.d if isinstance(b, Dual) else np.zeros(shape_n)
+        return Dual(np.where(cond, av, bv), np.where(cond[None, :], ad, bd))
+
 
 def val(x):
     """Value part of a Dual, or the array itself."""
@@ -81,41 +105,28 @@ def val(x):
 
 
 def exp(x):
-    if isinstance(x, Dual):
-        e = np.exp(x.v)
-        return Dual(e, x.d * e)
-    return np.exp(x)
+    return x._exp() if isinstance(x, Dual) else np.exp(x)
 
 
 def expm1(x):
-    if isinstance(x, Dual):
-        return Dual(np.expm1(x.v), x.d * np.exp(x.v))
-    return np.expm1(x)
+    return x._expm1() if isinstance(x, Dual) else np.expm1(x)
 
 
 def log(x):
-    if isinstance(x, Dual):
-        return Dual(np.log(x.v), x.d / x.v)
-    return np.log(x)
+    return x._log() if isinstance(x, Dual) else np.log(x)
 
 
 def sqrt(x):
-    if isinstance(x, Dual):
-        s = np.sqrt(x.v)
-        return Dual(s, x.d * (0.5 / s))
-    return np.sqrt(x)
+    return x._sqrt() if isinstance(x, Dual) else np.sqrt(x)
 
 
 def where(cond, a, b):
     """Pick a where cond else b, elementwise; cond is a boolean array computed
     from values only, so the derivative is that of the branch taken."""
-    if isinstance(a, Dual) or isinstance(b, Dual):
-        shape_n = (a.d if isinstance(a, Dual) else b.d).shape
-        av = val(a)
-        bv = val(b)
-        ad = a.d if isinstance(a, Dual) else np.zeros(shape_n)
-        bd = b.d if isinstance(b, Dual) else np.zeros(shape_n)
-        return Dual(np.where(cond, av, bv), np.where(cond[None, :], ad, bd))
+    if isinstance(a, Dual):
+        return type(a)._where(cond, a, b)
+    if isinstance(b, Dual):
+        return type(b)._where(cond, a, b)
     return np.where(cond, a, b)
 
 
