@@ -109,7 +109,7 @@ def run_pass_set(I, torch, w, steps, warmup):
     }
 
 
-def cpu_baseline(n_vertices=1024, n_steps=50):
+def cpu_baseline(n_vertices=2048, n_steps=120):
     """The oracle (fp64 numpy, single thread) on a bounded sample of the workload."""
     from threadpoolctl import threadpool_limits
 

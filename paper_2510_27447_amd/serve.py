@@ -1,3 +1,231 @@
-"""placeholder"""
-def run_trace(*a, **k):
-    return None
+"""Continuous-batching request loop for the reaction + SDC stage.
+
+Independent simulations (tissue or cell sweeps with their own vertex count,
+cell model, precision and dt) arrive over time.  The loop keeps every admitted
+simulation's ionic state resident in HBM and advances all simulations of one
+class (cell model x precision x node count, the unit one kernel instantiation
+serves) together: each round launches one batched kernel per class over a
+chunk of steps (reaction_sdc_step_batch), on one stream per class so the
+classes overlap on the GPU.  Between chunks it retires finished requests
+(their final V is read back) and admits arrivals in FIFO order while the
+resident footprint stays within the HBM budget and a slot is free.  A request
+computes exactly what it computes alone: every vertex's arithmetic is
+independent of what else shares the launch.
+
+Latency of a request = time its result (final V on the host) is ready minus
+its arrival time.  Throughput = total vertex-steps / (last completion - first
+arrival).
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional
+
+import numpy as np
+
+
+# ---- admission policy (pure host logic) ------------------------------------------
+class Admission:
+    """FIFO admission against a byte budget and a slot count."""
+
+    def __init__(self, budget_bytes: float, slots: int):
+        self.budget = float(budget_bytes)
+        self.slots = int(slots)
+        self.resident = 0.0
+        self.active = 0
+
+    def fits(self, footprint: float) -> bool:
+        return self.active < self.slots and self.resident + footprint <= self.budget
+
+    def admit(self, footprint: float):
+        if not self.fits(footprint):
+            raise RuntimeError("admission over budget or slots")
+        self.resident += footprint
+        self.active += 1
+
+    def release(self, footprint: float):
+        self.resident -= footprint
+        self.active -= 1
+
+    def take(self, waiting: deque, footprint_of):
+        """Pop the arrived requests that may start now (head-of-line FIFO).
+        A request larger than the whole budget is rejected (returned apart)."""
+        admitted, rejected = [], []
+        while waiting:
+            fp = footprint_of(waiting[0])
+            if fp > self.budget:
+                rejected.append(waiting.popleft())
+                continue
+            if not self.fits(fp):
+                break
+            self.admit(fp)
+            admitted.append(waiting.popleft())
+        return admitted, rejected
+
+
+@dataclass
+class _Job:
+    req: object
+    wl: object
+    sim: object
+    stim: object
+    diff: object
+    footprint: float
+    remaining: int
+    t_admit: float
+    result: Optional[np.ndarray] = None
+
+
+@dataclass
+class Result:
+    rid: int
+    model: str
+    precision: str
+    n: int
+    n_steps: int
+    arrival: float
+    admitted: float
+    done: float
+    V: Optional[np.ndarray] = None
+    state: Optional[np.ndarray] = None
+
+    @property
+    def latency(self):
+        return self.done - self.arrival
+
+
+@dataclass
+class Server:
+    budget_bytes: float = 200e9
+    slots: int = 64
+    chunk_steps: int = 100
+    keep_state: bool = False            # keep each result's full state (tests)
+    results: List[Result] = field(default_factory=list)
+    rejected: List[int] = field(default_factory=list)
+
+    def run(self, trace, verbose=False, time_scale=1.0):
+        """Serve the requests of `trace` (arrival times in seconds, replayed in
+        wall-clock time divided by time_scale).  Returns the list of Results."""
+        import torch
+
+        from . import ionic as I
+
+        policy = Admission(self.budget_bytes, self.slots)
+        streams: Dict[tuple, "torch.cuda.Stream"] = {}
+        upload = torch.cuda.Stream()
+        active: Dict[tuple, List[_Job]] = {}
+        inflight: Dict[tuple, "torch.cuda.Event"] = {}
+        pending = deque(sorted(trace, key=lambda r: r.arrival))
+        waiting: deque = deque()
+        t0 = time.perf_counter()
+
+        def now():
+            return (time.perf_counter() - t0) * time_scale
+
+        def start(req):
+            w = req.materialize()
+            with torch.cuda.stream(upload):
+                sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
+                                   newton_maxit=w.newton_maxit, stream=upload)
+                stim = torch.as_tensor(w.i_stim).to("cuda", non_blocking=False)
+                diff = torch.as_tensor(w.i_diff).to("cuda", non_blocking=False)
+            upload.synchronize()
+            I.ionic_set_inputs(sim.handle, 0.0, w.dt, w.n_nodes, w.n_sweeps, stim, w.stim_t_on,
+                               w.stim_t_off, diff)
+            return _Job(req, w, sim, stim, diff, req.footprint_bytes(), w.n_steps, now())
+
+        def finish(cls, job):
+            st = streams[cls]
+            with torch.cuda.stream(st):
+                if self.keep_state:
+                    state = job.sim.readback(stream=st)
+                    V = state[0].copy()
+                else:
+                    out = torch.empty((job.sim.n_states, job.sim.n), dtype=torch.float64, device="cuda")
+                    I.state_readback(job.sim.handle, job.sim.n_states, 0, job.sim.n, out=out, stream=st)
+                    V = out[0].cpu().numpy()
+                    state = None
+            r = job.req
+            self.results.append(Result(r.rid, r.model, r.precision, r.n, r.n_steps, r.arrival,
+                                       job.t_admit, now(), V, state))
+            job.sim.close()
+            policy.release(job.footprint)
+
+        while pending or waiting or any(active.values()):
+            t = now()
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.popleft())
+            progressed = False
+            # chunks that completed
+            for cls in list(inflight):
+                if inflight[cls].query():
+                    del inflight[cls]
+                    progressed = True
+            # retire finished jobs of idle classes
+            for cls, jobs in active.items():
+                if cls in inflight:
+                    continue
+                for job in [j for j in jobs if j.remaining == 0]:
+                    finish(cls, job)
+                    jobs.remove(job)
+                    progressed = True
+            # admit arrivals
+            adm, rej = policy.take(waiting, lambda r: r.footprint_bytes())
+            self.rejected += [r.rid for r in rej]
+            for req in adm:
+                cls = (req.model, req.precision, req.n_nodes)
+                if cls not in streams:
+                    streams[cls] = torch.cuda.Stream()
+                active.setdefault(cls, []).append(start(req))
+                progressed = True
+                if verbose:
+                    print("[serve] t=%.2fs admit req %d (%s %s N=%d steps=%d), active %d" % (
+                        now(), req.rid, req.model, req.precision, req.n, req.n_steps,
+                        policy.active), flush=True)
+            # launch the next chunk of every idle class
+            for cls, jobs in active.items():
+                if cls in inflight or not jobs:
+                    continue
+                steps = [min(self.chunk_steps, j.remaining) for j in jobs]
+                st = streams[cls]
+                I.reaction_sdc_step_batch([j.sim.handle for j in jobs], steps, stream=st)
+                ev = torch.cuda.Event()
+                ev.record(st)
+                inflight[cls] = ev
+                for j, k in zip(jobs, steps):
+                    j.remaining -= k
+                progressed = True
+            if not progressed:
+                time.sleep(0.0005)
+        torch.cuda.synchronize()
+        return self.results
+
+
+def summarize(results, rejected=()):
+    lat = np.array([r.latency for r in results])
+    work = sum(r.n * r.n_steps for r in results)
+    t_first = min(r.arrival for r in results)
+    t_last = max(r.done for r in results)
+    return {
+        "requests": len(results),
+        "rejected": len(rejected),
+        "p50_latency_s": float(np.percentile(lat, 50)),
+        "p99_latency_s": float(np.percentile(lat, 99)),
+        "mean_latency_s": float(lat.mean()),
+        "mean_queue_s": float(np.mean([r.admitted - r.arrival for r in results])),
+        "makespan_s": t_last - t_first,
+        "throughput_vertex_steps_per_s": work / (t_last - t_first),
+        "total_vertex_steps": int(work),
+    }
+
+
+def run_trace(trace, verbose=False, **server_kw):
+    srv = Server(**server_kw)
+    res = srv.run(trace, verbose=verbose)
+    out = summarize(res, srv.rejected)
+    out.update({"budget_bytes": srv.budget_bytes, "slots": srv.slots, "chunk_steps": srv.chunk_steps,
+                "trace": "256 requests, Poisson 20/s, N log-uniform [1e3, 2e6], LR91/TT06, "
+                         "fp64/mixed, dt {0.01, 0.02}, steps U{100..1000}, M=3, K=2"})
+    return out

@@ -143,9 +143,34 @@ def c4_tt06_spiral(seed=0, nx=200, ny=200, nz=200, n_steps=1000, precision="fp64
 
 @dataclass
 class Request:
+    """One serving request; its arrays are generated only when it is admitted."""
     rid: int
     arrival: float      # seconds after the trace starts
-    workload: Workload
+    model: str
+    precision: str
+    n: int
+    dt: float
+    n_steps: int
+    seed: int
+    n_nodes: int = 3
+    n_sweeps: int = 2
+
+    def footprint_bytes(self):
+        n_states = len(STATE_NAMES[self.model])
+        n_fp64 = 2 if self.model == "LR91" else 6
+        stride = (self.n + 63) // 64 * 64
+        per = n_states * 8 if self.precision == "fp64" else n_fp64 * 8 + (n_states - n_fp64) * 4
+        return stride * per + 2 * 8 * self.n          # state + stimulus + diffusion input
+
+    def materialize(self) -> Workload:
+        rng = np.random.Generator(np.random.PCG64(self.seed))
+        x0 = np.tile(initial_state(self.model)[:, None], (1, self.n))
+        stim = np.zeros(self.n)
+        stim[: max(1, self.n // 10)] = -80.0 if self.model == "LR91" else -100.0
+        diff = rng.normal(0.0, 0.5, self.n)
+        return Workload("C5-req%d" % self.rid, self.model, self.precision, x0, self.dt,
+                        self.n_steps, self.n_nodes, self.n_sweeps, 1e-10, 10, stim, 0.0, 1.0,
+                        diff, seed=self.seed)
 
 
 def c5_trace(seed=0, n_requests=256, rate_per_s=20.0, n_min=1e3, n_max=2e6):
@@ -159,13 +184,6 @@ def c5_trace(seed=0, n_requests=256, rate_per_s=20.0, n_min=1e3, n_max=2e6):
         dt = 0.01 if rng.random() < 0.5 else 0.02
         steps = int(rng.integers(100, 1001))
         precision = "fp64" if rng.random() < 0.5 else "mixed"
-        rs = int(rng.integers(0, 2 ** 31))
-        sub = np.random.Generator(np.random.PCG64(rs))
-        x0 = np.tile(initial_state(model)[:, None], (1, n))
-        stim = np.zeros(n)
-        stim[: max(1, n // 10)] = -80.0 if model == "LR91" else -100.0
-        diff = sub.normal(0.0, 0.5, n)
-        w = Workload("C5-req%d" % k, model, precision, x0, dt, steps, 3, 2, 1e-10, 10,
-                     stim, 0.0, 1.0, diff, seed=rs)
-        reqs.append(Request(k, float(arrivals[k]), w))
+        reqs.append(Request(k, float(arrivals[k]), model, precision, n, dt, steps,
+                            int(rng.integers(0, 2 ** 31))))
     return reqs
