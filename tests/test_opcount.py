@@ -1,0 +1,38 @@
+"""The flop constants bench.py uses equal what the oracle's op counter
+computes, and the counter itself counts sensibly (F+J costs more than F,
+the solve count follows the pattern's fill)."""
+import importlib.util
+import os
+
+from oracle import rest, tt06
+from oracle.models import LR91, TT06
+from oracle.opcount import per_evaluation, solve_flops
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_bench_constants_match_the_counter():
+    b = _bench()
+    for model, x, n64, const in ((TT06, tt06.published_initial(), 6, b.TT06_FLOPS),
+                                 (LR91, rest.lr91_rest(), 2, b.LR91_FLOPS)):
+        ev = per_evaluation(model, x, n64)
+        assert {k: ev[k] for k in ("F", "FJ", "solve")} == const, model.name
+        assert ev["FJ"] > ev["F"]
+    assert per_evaluation(TT06, tt06.published_initial(), 6)["nnz"] == 76
+
+
+def test_solve_count_on_a_tiny_pattern():
+    # 2x2 dense core, one gate depending on V (state 0): gate eliminated first
+    pattern = [[0, 1, 2], [0, 1], [0, 2]]
+    flops, nnz = solve_flops(pattern, 2)
+    # gate pivot: rcp; V row: l, a_VV update (2), b_V update (2); core: V pivot rcp, Cai row
+    # l + 1 update(2)+b(2), Cai pivot rcp; back substitution: 3 rows
+    assert nnz == 7
+    assert flops == (1 + 1 + 2 + 2) + (1 + 1 + 2 + 2) + 1 + (2 * 1 + 1) + (2 * 0 + 1) + (2 * 1 + 1)
