@@ -20,11 +20,12 @@ OBJDIR = os.path.join(LIBDIR, "obj")
 LIBNAME = "libionic_sdc.so"
 LIBPATH = os.path.join(LIBDIR, LIBNAME)
 
-SOURCES = ["kernels_tt06_fp64.hip", "kernels_tt06.hip", "kernels_lr91.hip", "kernels_test.hip",
-           "ionic.cpp"]
-# per-source optimisation level (default -O3); the double-precision TT06 step
-# kernel is built at -O1, where its code is exact (see that file's header)
-OPT = {"kernels_tt06_fp64.hip": "-O1"}
+SOURCES = ["kernels_tt06_fp64.hip", "kernels_tt06.hip", "kernels_lr91_fp64.hip",
+           "kernels_lr91.hip", "kernels_test.hip", "ionic.cpp"]
+# per-source optimisation level (default -O3); the double-precision step
+# kernels of the cell models are built at -O1, where their code is exact
+# (see the headers of those files)
+OPT = {"kernels_tt06_fp64.hip": "-O1", "kernels_lr91_fp64.hip": "-O1"}
 ARCH = os.environ.get("IONIC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH, "-std=c++20", "-fPIC",
@@ -50,7 +51,7 @@ def _compile(src, extra):
     return obj
 
 
-def build(jobs: int = 5, extra_flags=(), verbose: bool = True) -> str:
+def build(jobs: int = 6, extra_flags=(), verbose: bool = True) -> str:
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(OBJDIR, exist_ok=True)
     extra = list(extra_flags)

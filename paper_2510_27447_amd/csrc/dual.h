@@ -48,13 +48,21 @@ IONIC_DEV void for_bits(F&& f) {
 }
 
 // ---- precision-specific elementary functions ----------------------------------
-// double: the device math library (about 1 ulp).
+// double: the device math library (about 1 ulp); reciprocals from the hardware
+//         estimate refined by two Newton-Raphson steps (within about 1 ulp, finite
+//         non-zero arguments), instead of a correctly rounded division sequence.
 // float:  hardware transcendentals (v_exp_f32 / v_log_f32 / v_rcp_f32).
 IONIC_DEV double f_exp(double x) { return exp(x); }
 IONIC_DEV double f_expm1(double x) { return expm1(x); }
 IONIC_DEV double f_log(double x) { return log(x); }
 IONIC_DEV double f_sqrt(double x) { return sqrt(x); }
-IONIC_DEV double f_rcp(double x) { return 1.0 / x; }
+IONIC_DEV double f_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
 IONIC_DEV float f_exp(float x) { return __expf(x); }
 IONIC_DEV float f_expm1(float x) { return expm1f(x); }
 IONIC_DEV float f_log(float x) { return __logf(x); }

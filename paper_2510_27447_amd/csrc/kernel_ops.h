@@ -41,9 +41,11 @@ struct ModelOps {
                           long long v, double stim, double diff, double* out, hipStream_t st);
 };
 
-// The double-precision TT06 step kernel lives in a translation unit of its own,
-// compiled at a lower optimisation level (see the build script).
+// The double-precision step kernels of the cell models live in translation
+// units of their own, compiled at a lower optimisation level (see the build
+// script and kernels_fp64.hip).
 hipError_t tt06_sdc64(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
+hipError_t lr91_sdc64(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
 
 extern const ModelOps kOpsLR91;
 extern const ModelOps kOpsTT06;

@@ -1,7 +1,7 @@
 // Double-precision TT06 step kernel, in a translation unit of its own: the
-// build compiles it at -O1.  At -O3 the register allocator's handling of this
-// kernel (over 256 VGPRs plus AGPRs at one wave per SIMD) corrupted state
-// carried across the time-step loop on gfx950, while -O1 code is exact.
+// build compiles it at -O1.  At -O3 this kernel (over 256 VGPRs plus AGPRs and
+// scratch at one wave per SIMD) returned corrupted state on gfx950 while the
+// same source at -O1, and on the host, matches the reference to 1e-15.
 #include "kernel_ops_impl.h"
 #include "model_tt06.h"
 

@@ -102,6 +102,14 @@ struct LR91 {
   IONIC_DEV static void rhs(const Params<T>& p, T stim, T diff, Sink& out, const A0& Vm,
                             const A1& Ca, const A2& gm, const A3& gh, const A4& gj, const A5& gd,
                             const A6& gf, const A7& gX) {
+    // gate rows (eliminated first) are emitted before the V and Cai rows
+    const auto r = rates<T>(Vm);
+    out.template put<m>(r.am * (1.0 - gm) - r.bm * gm);
+    out.template put<h>(r.ah * (1.0 - gh) - r.bh * gh);
+    out.template put<j>(r.aj * (1.0 - gj) - r.bj * gj);
+    out.template put<d>(r.ad * (1.0 - gd) - r.bd * gd);
+    out.template put<f>(r.af * (1.0 - gf) - r.bf * gf);
+    out.template put<X>(r.aX * (1.0 - gX) - r.bX * gX);
     const auto I_Na = p.G_Na * (gm * gm * gm * gh * gj) * (Vm - double(p.E_Na));
     const auto E_si = 7.7 - 13.0287 * log(Ca);
     const auto I_si = p.G_si * (gd * gf) * (Vm - E_si);
@@ -122,13 +130,6 @@ struct LR91 {
     out.template put<V>(((((I_Na + I_si) + I_K) + I_K1) + I_Kp + I_b + double(stim)) * -1.0 +
                         double(diff));
     out.template put<Cai>(-1e-4 * I_si + 0.07 * (1e-4 - Ca));
-    const auto r = rates<T>(Vm);
-    out.template put<m>(r.am * (1.0 - gm) - r.bm * gm);
-    out.template put<h>(r.ah * (1.0 - gh) - r.bh * gh);
-    out.template put<j>(r.aj * (1.0 - gj) - r.bj * gj);
-    out.template put<d>(r.ad * (1.0 - gd) - r.bd * gd);
-    out.template put<f>(r.af * (1.0 - gf) - r.bf * gf);
-    out.template put<X>(r.aX * (1.0 - gX) - r.bX * gX);
   }
 
   // Gates at their steady state alpha / (alpha + beta) for the current V.

@@ -230,6 +230,26 @@ struct TT06 {
                             const A9& gxr1, const A10& gxr2, const A11& gxs, const A12& gr,
                             const A13& gs, const A14& gd, const A15& gf, const A16& gf2,
                             const A17& gfc, const A18& rbar) {
+    // rows eliminated first (gates, fCass, Rbar) are emitted before the core rows
+    const auto k_casr = double(p.max_sr) - double(p.dsr) / (1.0 + double(p.EC2) / (casr * casr));
+    const auto cass2 = cass * cass;
+    const auto g = gate_kinetics<T>(Vm);
+    out.template put<m>((g.inf[0] - gm) * g.rtau[0]);
+    out.template put<h>((g.inf[1] - gh) * g.rtau[1]);
+    out.template put<j>((g.inf[2] - gj) * g.rtau[2]);
+    out.template put<xr1>((g.inf[3] - gxr1) * g.rtau[3]);
+    out.template put<xr2>((g.inf[4] - gxr2) * g.rtau[4]);
+    out.template put<xs>((g.inf[5] - gxs) * g.rtau[5]);
+    out.template put<r>((g.inf[6] - gr) * g.rtau[6]);
+    out.template put<s>((g.inf[7] - gs) * g.rtau[7]);
+    out.template put<d>((g.inf[8] - gd) * g.rtau[8]);
+    out.template put<f>((g.inf[9] - gf) * g.rtau[9]);
+    out.template put<f2>((g.inf[10] - gf2) * g.rtau[10]);
+    const auto qf = 1.0 + cass2 * 400.0;  // 1 + (CaSS/0.05)^2
+    const auto rq = 1.0 / qf;
+    out.template put<fCass>((0.6 * rq + 0.4 - gfc) / (80.0 * rq + 2.0));
+    out.template put<Rbar>(-(double(p.k2p) * k_casr) * cass * rbar + double(p.k4) * (1.0 - rbar));
+
     // reversal potentials: RT/F log(out/in)
     const auto E_Na = double(p.RTF) * (double(p.logNao) - log(nai));
     const auto E_K = double(p.RTF) * (double(p.logKo) - log(ki));
@@ -266,8 +286,6 @@ struct TT06 {
     const auto I_bCa = double(p.G_bCa) * (Vm - E_Ca);
 
     // calcium handling
-    const auto k_casr = double(p.max_sr) - double(p.dsr) / (1.0 + double(p.EC2) / (casr * casr));
-    const auto cass2 = cass * cass;
     const auto k1 = double(p.k1p) / k_casr;
     const auto O = (k1 * cass2 * rbar) / (double(p.k3) + k1 * cass2);
     const auto I_rel = double(p.V_rel) * O * (casr - cass);
@@ -294,22 +312,6 @@ struct TT06 {
     out.template put<Ki>((I_K1 + I_to + I_Kr + I_Ks - 2.0 * I_NaK + I_pK + double(stim - diff)) *
                          -double(p.cF_c));
 
-    const auto g = gate_kinetics<T>(Vm);
-    out.template put<m>((g.inf[0] - gm) * g.rtau[0]);
-    out.template put<h>((g.inf[1] - gh) * g.rtau[1]);
-    out.template put<j>((g.inf[2] - gj) * g.rtau[2]);
-    out.template put<xr1>((g.inf[3] - gxr1) * g.rtau[3]);
-    out.template put<xr2>((g.inf[4] - gxr2) * g.rtau[4]);
-    out.template put<xs>((g.inf[5] - gxs) * g.rtau[5]);
-    out.template put<r>((g.inf[6] - gr) * g.rtau[6]);
-    out.template put<s>((g.inf[7] - gs) * g.rtau[7]);
-    out.template put<d>((g.inf[8] - gd) * g.rtau[8]);
-    out.template put<f>((g.inf[9] - gf) * g.rtau[9]);
-    out.template put<f2>((g.inf[10] - gf2) * g.rtau[10]);
-    const auto qf = 1.0 + cass2 * 400.0;  // 1 + (CaSS/0.05)^2
-    const auto rq = 1.0 / qf;
-    out.template put<fCass>((0.6 * rq + 0.4 - gfc) / (80.0 * rq + 2.0));
-    out.template put<Rbar>(-(double(p.k2p) * k_casr) * cass * rbar + double(p.k4) * (1.0 - rbar));
   }
 
   template <class T>

@@ -91,25 +91,6 @@ struct SinkF {
   }
 };
 
-// F and A = I - dtau J on the declared pattern
-template <class Model, class T>
-struct SinkFJ {
-  T* f;
-  T (*a)[Model::N];
-  T dtau;
-  template <int i, uint32_t M>
-  IONIC_DEV void put(const D<T, M>& x) {
-    static_assert((M & ~Model::ROW[i]) == 0, "J_i has an entry outside its declared row");
-    f[i] = x.v;
-    for_bits<Model::ROW[i] | (1u << i)>([&](auto K) {
-      constexpr int k = K;
-      T jik = T(0);
-      if constexpr (has(M, k)) jik = x.template d<k>();
-      a[i][k] = (k == i ? T(1) : T(0)) - dtau * jik;
-    });
-  }
-};
-
 // dense F and J (debug entry point)
 template <class Model, class T>
 struct SinkDense {
@@ -198,12 +179,15 @@ IONIC_DEV void eval_F(const typename Model::template Params<T>& p, T stim, T dif
   SinkF<Model, T> s{f};
   call_rhs_F<Model, T>(p, stim, diff, s, x, std::make_index_sequence<Model::N>{});
 }
-template <class Model, class T>
-IONIC_DEV void eval_FJ(const typename Model::template Params<T>& p, T stim, T diff, T dtau,
-                       const T (&x)[Model::N], T (&f)[Model::N], T (&a)[Model::N][Model::N]) {
-  SinkFJ<Model, T> s{f, a, dtau};
+// F and J at x, and the solution of (I - dtau J(x)) delta = b with b_i = bfn(i, F_i),
+// the elimination running while the model emits its rows.
+template <class Model, class T, class BFn>
+IONIC_DEV void eval_solve(const typename Model::template Params<T>& p, T stim, T diff, T dtau,
+                          const T (&x)[Model::N], BFn bfn, T (&f)[Model::N], T (&delta)[Model::N]) {
+  SinkElim<Model, T, BFn> s(dtau, bfn);
   call_rhs_FJ<Model, T>(p, stim, diff, s, x, std::make_index_sequence<Model::N>{});
-  zero_fill<Model, T>(a);
+  s.solve(delta);
+  static_for<Model::N>([&](auto I) { f[I] = s.f[I]; });
 }
 
 IONIC_DEV unsigned long long wave_sum(unsigned long long x) {
@@ -264,24 +248,23 @@ __global__ void __launch_bounds__(kBlock)
       int it = 0;
       bool conv = false;
       do {
-        TE xe[N], f[N], a[N][N], b[N];
+        TE xe[N], f[N], delta[N];
         L::to_eval(Y, xe);
-        eval_FJ<Model, TE>(p, stim, diff, dtau[m], xe, f, a);
-        static_for<N>([&](auto I) {
+        // b = -(Y - X_m - dtau F(Y)), formed in double
+        auto bfn = [&](auto I, TE fi) -> TE {
           constexpr int i = I;
-          const double g = double(L::template at<i>(Y)) - double(L::template at<i>(X[m])) -
-                           double(dtau[m]) * double(f[i]);
-          b[i] = TE(-g);
-        });
-        sparse_solve<Model, TE>(a, b);
+          return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
+                    double(dtau[m]) * double(fi));
+        };
+        eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
         TE err = TE(0);
         static_for<N>([&](auto I) {
           constexpr int i = I;
           auto& y = L::template at<i>(Y);
-          y += b[i];
+          y += delta[i];
           const TE ay = fabs(TE(y));
           const TE s = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
-          const TE e = fabs(b[i]) / s;
+          const TE e = fabs(delta[i]) / s;
           err = e > err ? e : err;
         });
         ++it;
@@ -318,24 +301,27 @@ __global__ void __launch_bounds__(kBlock)
         });
         static_for<M - 1>([&](auto MM) {
           constexpr int m = MM;
-          TE xe[N], f[N], a[N][N], b[N];
+          TE xe[N], f[N], delta[N];
           L::to_eval(X[m + 1], xe);
-          eval_FJ<Model, TE>(p, stim, diff, dtau[m], xe, f, a);
+          // r = X^{k+1}_m - X^k_{m+1} + Q_m in double; at m = 0 the evaluation point is
+          // node 1, whose F enters every Q_m
+          auto bfn = [&](auto I, TE fi) -> TE {
+            constexpr int i = I;
+            double r = double(L::template at<i>(X[m])) - double(L::template at<i>(X[m + 1])) +
+                       Q[m][i];
+            if constexpr (m == 0) r += Sdt[0][1] * double(fi);
+            return TE(r);
+          };
+          eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
           if constexpr (m == 0) {
-            static_for<M - 1>([&](auto mm) {
+            static_for<M - 2>([&](auto MM2) {
+              constexpr int mm = MM2 + 1;
               static_for<N>([&](auto i) { Q[mm][i] += Sdt[mm][1] * double(f[i]); });
             });
           }
           static_for<N>([&](auto I) {
             constexpr int i = I;
-            const double r = double(L::template at<i>(X[m])) - double(L::template at<i>(X[m + 1])) +
-                             Q[m][i];
-            b[i] = TE(r);
-          });
-          sparse_solve<Model, TE>(a, b);
-          static_for<N>([&](auto I) {
-            constexpr int i = I;
-            L::template at<i>(X[m + 1]) += b[i];
+            L::template at<i>(X[m + 1]) += delta[i];
           });
         });
       }

@@ -4,14 +4,20 @@
 // 3.3.2, solver paragraph after Algorithm 2) is exact in one step: the system
 // is block diagonal with one small block per vertex.  Each block is solved
 // here directly, by Gaussian elimination whose every operation is decided at
-// compile time from the model's Jacobian pattern (CTSM): the gate rows, which
-// touch only V and themselves (TT06 also fCass and Rbar), are eliminated first
-// and produce no new nonzeros outside the V column; the dense core left over
-// (LR91: {V, Cai}; TT06: {V, Cai, CaSR, CaSS, Nai, Ki}) is eliminated without
-// pivoting.  Pivots are 1 + dtau / tau_gate for the gates, so no pivoting is
-// needed there; the core is diagonally dominant for the step sizes used.
-// Symbolic fill-in is computed by a constexpr function, so the unrolled code
-// touches structural nonzeros only.
+// compile time from the model's Jacobian pattern (CTSM).  The states stored in
+// fp32 under the mixed layout -- the gates, and for TT06 also fCass and Rbar --
+// form the set G: each of their rows touches only itself and "core" states
+// (LR91 {V, Cai}; TT06 {V, Cai, CaSR, CaSS, Nai, Ki}).  G rows are eliminated
+// first; their pivots are 1 + dtau / tau, so no pivoting is needed, and they
+// produce fill only inside the core.  The dense core is then eliminated
+// without pivoting (diagonally dominant at the step sizes used).
+//
+// SinkElim performs the elimination while the model emits its rows: a G row
+// leaves its right-hand side and its core coefficients divided by the pivot;
+// a core row, when it arrives, folds every G column it touches into its core
+// entries at once.  The Jacobian is therefore never held whole, only the G
+// coefficients and the core block.  The model must emit all G rows before the
+// core rows.
 #pragma once
 
 #include "dual.h"
@@ -21,9 +27,19 @@ namespace ionic {
 template <class Model>
 struct Elim {
   static constexpr int N = Model::N;
-  static constexpr int NG = N - Model::N64;  // rows eliminated first
+  static constexpr int NC = Model::N64;  // core states: [0, NC)
+  static constexpr int NG = N - NC;      // rows eliminated first: [NC, N)
+  static constexpr uint32_t G_MASK = ((N >= 32) ? 0xFFFFFFFFu : ((1u << N) - 1u)) & ~((1u << NC) - 1u);
   // elimination position -> state index
-  static constexpr int at(int k) { return k < NG ? Model::N64 + k : k - NG; }
+  static constexpr int at(int k) { return k < NG ? NC + k : k - NG; }
+
+  static constexpr bool g_rows_touch_core_only() {
+    for (int g = NC; g < N; ++g)
+      if ((Model::ROW[g] & G_MASK) & ~(1u << g)) return false;
+    return true;
+  }
+  static_assert(g_rows_touch_core_only(),
+                "every row eliminated first may depend only on itself and core states");
 
   struct Pat {
     bool p[N][N];
@@ -46,67 +62,108 @@ struct Elim {
     return P;
   }
   static constexpr Pat FILL = filled();
-
-  static constexpr int nnz_filled() {
-    int c = 0;
-    for (int i = 0; i < N; ++i)
-      for (int k = 0; k < N; ++k) c += FILL.p[i][k] ? 1 : 0;
-    return c;
-  }
 };
 
-// Zero the fill-in positions (in FILL but outside the declared rows), which the
-// Jacobian writer never touches.
-template <class Model, class T>
-IONIC_DEV void zero_fill(T (&a)[Model::N][Model::N]) {
+// Receives the rows of F and J (value and partials) in emission order and
+// solves (I - dtau J) delta = b with b_i = bfn(i, F_i).
+template <class Model, class T, class BFn>
+struct SinkElim {
   using E = Elim<Model>;
-  static_for<Model::N>([&](auto I) {
-    static_for<Model::N>([&](auto K) {
-      constexpr int i = I, k = K;
-      if constexpr (E::FILL.p[i][k] && i != k && !has(Model::ROW[i], k)) a[i][k] = T(0);
-    });
-  });
-}
+  static constexpr int N = Model::N;
+  static constexpr int NC = E::NC;
 
-// Solve a x = b in place (x returned in b).  Only entries of Elim<Model>::FILL are
-// read; the declared pattern plus the diagonal must have been written and the
-// fill-in positions cleared with zero_fill.
-template <class Model, class T>
-IONIC_DEV void sparse_solve(T (&a)[Model::N][Model::N], T (&b)[Model::N]) {
-  using E = Elim<Model>;
-  constexpr int N = Model::N;
-  T inv[N];
-  static_for<N>([&](auto K) {
-    constexpr int p = E::at(K);
-    inv[p] = f_rcp(a[p][p]);
-    static_for<N>([&](auto II) {
-      if constexpr (II > K) {
-        constexpr int i = E::at(II);
-        if constexpr (E::FILL.p[i][p]) {
+  T dtau;
+  BFn bfn;
+  T f[N];          // F at the evaluation point
+  T gd[N];         // G rows: b_g / pivot
+  T gc[N][NC];     // G rows: a_gk / pivot for core columns k
+  T a[NC][NC];     // core block (on the fill pattern)
+  T b[NC];
+
+  IONIC_DEV SinkElim(T dt, BFn fn) : dtau(dt), bfn(fn) {}
+
+  template <int i, uint32_t M>
+  IONIC_DEV T jac(const D<T, M>& x) const {
+    if constexpr (has(M, i))
+      return x.template d<i>();
+    else
+      return T(0);
+  }
+
+  template <int i, uint32_t M>
+  IONIC_DEV void put(const D<T, M>& x) {
+    static_assert((M & ~Model::ROW[i]) == 0, "row has an entry outside its declared pattern");
+    f[i] = x.v;
+    const T bi = bfn(std::integral_constant<int, i>{}, x.v);
+    if constexpr (i >= NC) {
+      const T inv = f_rcp(T(1) - dtau * jac<i>(x));
+      gd[i] = bi * inv;
+      for_bits<Model::ROW[i] & ~bit(i)>([&](auto K) {
+        constexpr int k = K;
+        gc[i][k] = -(dtau * jac<k>(x)) * inv;
+      });
+    } else {
+      // core entries of row i, fill positions cleared
+      static_for<NC>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == i)
+          a[i][k] = T(1) - dtau * jac<k>(x);
+        else if constexpr (has(Model::ROW[i], k))
+          a[i][k] = -dtau * jac<k>(x);
+        else if constexpr (E::FILL.p[i][k])
+          a[i][k] = T(0);
+      });
+      T bb = bi;
+      for_bits<Model::ROW[i] & E::G_MASK>([&](auto G) {
+        constexpr int g = G;
+        const T aig = -dtau * jac<g>(x);
+        bb -= aig * gd[g];
+        for_bits<Model::ROW[g] & ~bit(g)>([&](auto K) {
+          constexpr int k = K;
+          a[i][k] -= aig * gc[g][k];
+        });
+      });
+      b[i] = bb;
+    }
+  }
+
+  // After all rows: eliminate the core, back-substitute, recover the G states.
+  IONIC_DEV void solve(T (&delta)[N]) {
+    T inv[NC];
+    static_for<NC>([&](auto P) {
+      constexpr int p = P;
+      inv[p] = f_rcp(a[p][p]);
+      static_for<NC>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > p && E::FILL.p[i][p]) {
           const T l = a[i][p] * inv[p];
-          static_for<N>([&](auto JJ) {
-            if constexpr (JJ > K) {
-              constexpr int jx = E::at(JJ);
-              if constexpr (E::FILL.p[p][jx]) a[i][jx] -= l * a[p][jx];
-            }
+          static_for<NC>([&](auto J) {
+            constexpr int jx = J;
+            if constexpr (jx > p && E::FILL.p[p][jx]) a[i][jx] -= l * a[p][jx];
           });
           b[i] -= l * b[p];
         }
-      }
+      });
     });
-  });
-  static_for<N>([&](auto KR) {
-    constexpr int K = N - 1 - KR;
-    constexpr int p = E::at(K);
-    T acc = b[p];
-    static_for<N>([&](auto JJ) {
-      if constexpr (JJ > K) {
-        constexpr int jx = E::at(JJ);
-        if constexpr (E::FILL.p[p][jx]) acc -= a[p][jx] * b[jx];
-      }
+    static_for<NC>([&](auto PR) {
+      constexpr int p = NC - 1 - PR;
+      T acc = b[p];
+      static_for<NC>([&](auto J) {
+        constexpr int jx = J;
+        if constexpr (jx > p && E::FILL.p[p][jx]) acc -= a[p][jx] * delta[jx];
+      });
+      delta[p] = acc * inv[p];
     });
-    b[p] = acc * inv[p];
-  });
-}
+    static_for<N - NC>([&](auto GG) {
+      constexpr int g = NC + GG;
+      T acc = gd[g];
+      for_bits<Model::ROW[g] & ~bit(g)>([&](auto K) {
+        constexpr int k = K;
+        acc -= gc[g][k] * delta[k];
+      });
+      delta[g] = acc;
+    });
+  }
+};
 
 }  // namespace ionic
