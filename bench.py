@@ -23,6 +23,8 @@ Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-serving] [--no-
 from __future__ import annotations
 
 import argparse
+import csv
+import hashlib
 import json
 import os
 import sys
@@ -37,6 +39,91 @@ TT06_FLOPS = {"F": 553, "FJ": 1250, "solve": 362}
 LR91_FLOPS = {"F": 232, "FJ": 465, "solve": 75}
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector fp64 / fp32 (published)
 HBM_PEAK_GBS = 8000.0
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(ROOT, "paper_2510_27447_amd", "csrc")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_sdc_kernel_tt06_slab1e6_500steps.txt")
+STATE_BYTES = {"fp64": 19 * 8 * 1_000_000, "mixed": (6 * 8 + 13 * 4) * 1_000_000}
+
+
+def kernel_source_hash():
+    """Hash of the kernel sources and build flags the traffic counters belong to."""
+    h = hashlib.sha1()
+    for fn in sorted(os.listdir(CSRC)):
+        if fn.endswith((".h", ".hip")):
+            h.update(fn.encode())
+            with open(os.path.join(CSRC, fn), "rb") as f:
+                h.update(f.read())
+    with open(os.path.join(ROOT, "paper_2510_27447_amd", "build.py"), "rb") as f:
+        h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_counters(fetch_csv, write_csv):
+    """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0`.
+    Each counter is scaled by what it reads for the state-restore copies of the
+    same run (__amd_rocclr_copyBuffer of a known number of bytes)."""
+    out = {}
+    for counter, path in (("fetch", fetch_csv), ("write", write_csv)):
+        rows = list(csv.DictReader(open(path)))
+        kern = {}
+        copies = []
+        for r in rows:
+            v = float(r["Counter_Value"]) * 1024.0
+            name = r["Kernel_Name"]
+            if "sdc_kernel" in name:
+                kern["fp64" if "Fp64" in name else "mixed"] = v
+            elif "copyBuffer" in name and v > 1e6:
+                copies.append(v)
+        # the two largest copy sizes are the fp64 and mixed state restores
+        factors = []
+        for prec, nbytes in STATE_BYTES.items():
+            near = [c for c in copies if 0.3 * nbytes < c < 1.5 * nbytes]
+            near_fp64 = prec == "fp64"
+            if near:
+                pick = max(near) if near_fp64 else min(near)
+                factors.append(nbytes / pick)
+        scale = float(np.median(factors))
+        for prec, v in kern.items():
+            out.setdefault(prec, {})[counter] = v * scale
+            out[prec][counter + "_scale"] = scale
+    return out
+
+
+def write_traffic_file(fetch_csv, write_csv):
+    t = traffic_from_counters(fetch_csv, write_csv)
+    lines = ["# HBM traffic of sdc_kernel<TT06, *, 3>, TT06 slab 1e6 vertices x 500 steps, per launch",
+             "# commands (repository root, MI355X):",
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/p5/fetch -o fetch -- "
+             "python3 bench.py --no-serving --no-cpu --steps 1 --warmup 0",
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/p5/write -o write -- "
+             "python3 bench.py --no-serving --no-cpu --steps 1 --warmup 0",
+             "#   python3 bench.py --traffic-from <fetch csv> <write csv>",
+             "# counters scaled by their reading for the state-restore copy (known bytes)",
+             "source_hash: %s" % kernel_source_hash()]
+    for prec in ("fp64", "mixed"):
+        d = t[prec]
+        lines.append("%s_fetch_bytes: %.6e" % (prec, d["fetch"]))
+        lines.append("%s_write_bytes: %.6e" % (prec, d["write"]))
+        lines.append("%s_fetch_scale: %.4f" % (prec, d["fetch_scale"]))
+        lines.append("%s_write_scale: %.4f" % (prec, d["write_scale"]))
+        lines.append("%s_algorithmic_bytes: %.6e" % (prec, 2 * STATE_BYTES[prec] + 16 * 1_000_000))
+    with open(TRAFFIC_FILE, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def read_traffic(prec):
+    """Per-launch HBM bytes (fetch + write) recorded for the current kernel sources, or None."""
+    try:
+        kv = dict(l.split(": ", 1) for l in open(TRAFFIC_FILE).read().splitlines()
+                  if l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("source_hash") != kernel_source_hash():
+        return None
+    return float(kv[prec + "_fetch_bytes"]) + float(kv[prec + "_write_bytes"])
 
 
 def flops_per_launch(ev, n_states, vertex_steps, M, K, newton_iters):
@@ -102,8 +189,9 @@ def run_pass_set(I, torch, w, steps, warmup):
         "roofline": {
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[w.precision],
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[w.precision], 4),
-            "traffic": None,
+            "traffic": read_traffic(w.precision),
         },
+        "traffic_algorithmic_bytes": bytes_launch,
         "hbm_gbs_algorithmic": bytes_launch / kavg / 1e9,
         "V": V,
     }
@@ -141,7 +229,12 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic_file(*args.traffic_from)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the reaction stage shards by vertex ranges with no "
               "exchange, and this build runs and reports a single MI355X only (--gpus 1).",
@@ -205,6 +298,7 @@ def main():
         "mixed_vs_fp64_V_error": mixed_err,
         "newton_iters_per_solve": m["newton_iters_per_solve"],
         "roofline": m["roofline"],
+        "traffic_algorithmic_bytes": m["traffic_algorithmic_bytes"],
         "hbm_gbs_algorithmic": m["hbm_gbs_algorithmic"],
         "cpu_baseline": cpu,
         "serving": serving,
