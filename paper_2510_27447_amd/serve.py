@@ -18,6 +18,7 @@ arrival).
 """
 from __future__ import annotations
 
+import sys
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -183,7 +184,7 @@ class Server:
                 if verbose:
                     print("[serve] t=%.2fs admit req %d (%s %s N=%d steps=%d), active %d" % (
                         now(), req.rid, req.model, req.precision, req.n, req.n_steps,
-                        policy.active), flush=True)
+                        policy.active), file=sys.stderr, flush=True)
             # launch the next chunk of every idle class
             for cls, jobs in active.items():
                 if cls in inflight or not jobs:
