@@ -7,13 +7,16 @@ nodal evaluation of the reaction terms).  One step from t_n to t_n + dt:
 
 1. nodes c_0 = 0 < ... < c_{M-1} = 1 (Gauss-Lobatto), sub-steps
    dtau_m = (c_{m+1} - c_m) dt, quadrature S * dt (module lobatto);
-2. predictor: X_0 = X_n and, for each sub-interval, backward Euler
-   Y - X_m - dtau_m F(Y) = 0 solved by local Newton
-   (I - dtau_m J(Y)) delta = -(Y - X_m - dtau_m F(Y)),  Y += delta,
-   stopping once max_i |delta_i| / max(|Y_i|, scale_i) <= tol (at least one
-   iteration, at most maxit, the last iterate kept);
-   the paper's predictor is a Rosenbrock method (equation rb_system); the
-   first-order implicit predictor is the one its correction equation uses;
+2. predictor, X_0 = X_n and, on each sub-interval, either
+   (a) backward Euler Y - X_m - dtau_m F(Y) = 0 solved by local Newton
+       (I - dtau_m J(Y)) delta = -(Y - X_m - dtau_m F(Y)),  Y += delta,
+       stopping once max_i |delta_i| / max(|Y_i|, scale_i) <= tol (at least
+       one iteration, at most maxit, the last iterate kept): the first-order
+       implicit integrator the paper's correction equation uses; or
+   (b) one step of the Rosenbrock method ROS2 (equation rb_system, module
+       ros2), the paper's own predictor, which also yields the scaled
+       embedded error max_i |X_i - X_hat_i| / max(|X_i|, scale_i) used for
+       step-size control;
 3. K sweeps of the linearised implicit correction (equations residual,
    sdc_ode, sdc generalised from the trapezoid to M nodes):
    F^k_j = F(X^k_j);  X^{k+1}_0 = X_n;  for m = 0..M-2
@@ -33,6 +36,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 from .lobatto import integration_matrix, nodes
+from .ros2 import ros2_step
 
 
 @dataclass
@@ -43,6 +47,7 @@ class Stats:
     n_nonconverged: int = 0
     n_nonfinite: int = 0
     per_vertex_iters: np.ndarray = field(default=None, repr=False)
+    embedded_error: list = field(default_factory=list, repr=False)
 
 
 def _solve(A, b):
@@ -90,15 +95,37 @@ def _pick(a, idx):
     return a[idx]
 
 
-def sdc_step(model, Xn, i_stim, dt, M, K, i_diff, tol, maxit, clamp_v, stats, S, c):
+def embedded_error(model, X, X_hat):
+    """Scaled embedded error per vertex: max_i |X_i - X_hat_i| / max(|X_i|, scale_i)."""
+    scale = model.newton_scale[:, None]
+    return np.max(np.abs(X - X_hat) / np.maximum(np.abs(X), scale), axis=0)
+
+
+PREDICTORS = ("newton", "ros2")
+
+
+def sdc_step(model, Xn, i_stim, dt, M, K, i_diff, tol, maxit, clamp_v, stats, S, c,
+             predictor="newton"):
+    """One step; returns X_{n+1} and, for the ROS2 predictor, the embedded error
+    per vertex (largest over the sub-intervals; None for Newton)."""
     n, N = Xn.shape
     I = np.eye(n)
     dtau = np.diff(c) * dt
     Sdt = S * dt
     # predictor
     Xk = [Xn]
-    for m in range(M - 1):
-        Xk.append(newton_be(model, Xk[m], dtau[m], i_stim, i_diff, tol, maxit, clamp_v, stats))
+    err = None
+    if predictor == "newton":
+        for m in range(M - 1):
+            Xk.append(newton_be(model, Xk[m], dtau[m], i_stim, i_diff, tol, maxit, clamp_v, stats))
+    elif predictor == "ros2":
+        err = np.zeros(N)
+        for m in range(M - 1):
+            Xnew, Xhat, _ = ros2_step(model, Xk[m], dtau[m], i_stim, i_diff, clamp_v)
+            err = np.maximum(err, embedded_error(model, Xnew, Xhat))
+            Xk.append(Xnew)
+    else:
+        raise ValueError("unknown predictor %r" % (predictor,))
     # corrections
     F0 = model.F(Xn, i_stim, i_diff, clamp_v)
     for _ in range(K):
@@ -112,13 +139,15 @@ def sdc_step(model, Xn, i_stim, dt, M, K, i_diff, tol, maxit, clamp_v, stats, S,
             delta = _solve(I[None] - dtau[m] * J, r.T).T
             Xnew.append(Xk[m + 1] + delta)
         Xk = Xnew
-    return Xk[M - 1]
+    return Xk[M - 1], err
 
 
 def advance(model, X0, *, t0=0.0, dt, n_steps, n_nodes, n_sweeps,
             i_stim=None, stim_on=0.0, stim_off=0.0, i_diff=None,
-            tol=1e-10, maxit=10, clamp_v=False):
-    """Advance X0 (n, N) by n_steps steps; returns (X, Stats)."""
+            tol=1e-10, maxit=10, clamp_v=False, predictor="newton"):
+    """Advance X0 (n, N) by n_steps steps of size dt; returns (X, Stats).  With
+    the ROS2 predictor, Stats.embedded_error holds the largest scaled embedded
+    error over the vertices, one entry per step."""
     X = np.array(X0, dtype=np.float64, copy=True)
     n, N = X.shape
     if n != model.n:
@@ -130,6 +159,9 @@ def advance(model, X0, *, t0=0.0, dt, n_steps, n_nodes, n_sweeps,
     stats = Stats(per_vertex_iters=np.zeros(N, dtype=np.int64))
     for step in range(n_steps):
         stim = stim_amp if stimulus_on(t0, dt, step, stim_on, stim_off) else np.zeros(N)
-        X = sdc_step(model, X, stim, dt, n_nodes, n_sweeps, diff, tol, maxit, clamp_v, stats, S, c)
+        X, err = sdc_step(model, X, stim, dt, n_nodes, n_sweeps, diff, tol, maxit, clamp_v, stats,
+                          S, c, predictor)
+        if err is not None:
+            stats.embedded_error.append(float(np.max(err, initial=0.0)))
     stats.n_nonfinite = int((~np.isfinite(X).all(axis=0)).sum())
     return X, stats
