@@ -35,8 +35,8 @@ import numpy as np
 # Operation counts per evaluation of the TT06 model (forward-mode
 # differentiation on the compile-time Jacobian pattern; printed by
 # `python -m oracle.opcount`, checked against it by the CPU tests).
-TT06_FLOPS = {"F": 553, "FJ": 1250, "solve": 362}
-LR91_FLOPS = {"F": 232, "FJ": 465, "solve": 75}
+TT06_FLOPS = {"F": 553, "FJ": 1250, "solve": 362, "resolve": 155}
+LR91_FLOPS = {"F": 232, "FJ": 465, "solve": 75, "resolve": 40}
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector fp64 / fp32 (published)
 HBM_PEAK_GBS = 8000.0
 
@@ -133,13 +133,24 @@ def flops_per_launch(ev, n_states, vertex_steps, M, K, newton_iters):
             + vertex_steps * K * ((M - 1) * M * 2 + (M - 1) * 3) * n_states)
 
 
+def flops_per_launch_ros2(ev, n_states, vertex_steps, M, K):
+    """ROS2 predictor: per sub-interval one F+J evaluation with its elimination,
+    one F evaluation, one second solve and 12 flops of stage arithmetic per
+    state; sweeps as above but F(X_n) comes from the first stage."""
+    per_sub = ev["FJ"] + ev["solve"] + ev["F"] + ev["resolve"] + 12 * n_states
+    sweeps = (K * (M - 2) * ev["F"] + K * (M - 1) * (ev["FJ"] + ev["solve"])
+              + K * ((M - 1) * M * 2 + (M - 1) * 3) * n_states)
+    return vertex_steps * ((M - 1) * per_sub + sweeps)
+
+
 def state_bytes_per_vertex(precision):
     return 19 * 8 if precision == "fp64" else 6 * 8 + 13 * 4
 
 
-def run_pass_set(I, torch, w, steps, warmup):
+def run_pass_set(I, torch, w, steps, warmup, predictor="newton"):
     sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
                        newton_maxit=w.newton_maxit)
+    sim.set_predictor(predictor)
     stim = torch.as_tensor(w.i_stim).cuda()
     diff = torch.as_tensor(w.i_diff).cuda()
     init = sim.state.clone()
@@ -172,7 +183,10 @@ def run_pass_set(I, torch, w, steps, warmup):
     sim.close()
     vsteps = w.n * w.n_steps
     iters = st["newton_iters"] / steps
-    flops = flops_per_launch(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps, iters)
+    if predictor == "newton":
+        flops = flops_per_launch(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps, iters)
+    else:
+        flops = flops_per_launch_ros2(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps)
     kavg = float(np.mean(kernel_ms)) / 1e3
     achieved = flops / kavg / 1e12
     bytes_launch = w.n * (2 * state_bytes_per_vertex(w.precision) + 2 * 8)  # state r/w, stim, diff
@@ -189,10 +203,52 @@ def run_pass_set(I, torch, w, steps, warmup):
         "roofline": {
             "bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_TFLOPS[w.precision],
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[w.precision], 4),
-            "traffic": read_traffic(w.precision),
+            "traffic": read_traffic(w.precision) if predictor == "newton" else None,
         },
         "traffic_algorithmic_bytes": bytes_launch,
         "hbm_gbs_algorithmic": bytes_launch / kavg / 1e9,
+        "V": V,
+    }
+
+
+def run_adaptive(I, torch, w, err_tol, t_end, dt_max, dt_init=0.01):
+    """The paper's scheme with adaptive steps over [0, t_end] on the same slab:
+    ROS2 predictor, 2 nodes, 1 correction, one step size for all vertices.
+    One untimed run, then one timed run from the same initial state."""
+    sim = I.Simulation(w.model, w.x0, precision=w.precision)
+    stim = torch.as_tensor(w.i_stim).cuda()
+    diff = torch.as_tensor(w.i_diff).cuda()
+    init = sim.state.clone()
+    stream = torch.cuda.current_stream()
+
+    def run():
+        sim.state.copy_(init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = sim.adaptive(0.0, t_end, dt_init, dt_max, err_tol, n_nodes=2, n_sweeps=1,
+                         i_stim=stim, stim_t_on=w.stim_t_on, stim_t_off=w.stim_t_off,
+                         i_diff=diff, stream=stream)
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    run()
+    I.ionic_reset_stats(sim.handle)
+    r, wall = run()
+    st = sim.stats()
+    V = sim.readback()[0]
+    sim.close()
+    attempts = r["accepted"] + r["rejected"]
+    flops = flops_per_launch_ros2(TT06_FLOPS, 19, w.n * attempts, 2, 1)
+    achieved = flops / wall / 1e12
+    return {
+        "err_tol": err_tol, "t_end_ms": t_end, "dt_max_ms": dt_max,
+        "accepted": r["accepted"], "rejected": r["rejected"], "reached": r["reached"],
+        "wall_s": wall, "simulated_ms_per_s": t_end / wall,
+        "vertex_steps_per_s": w.n * r["accepted"] / wall,
+        "mean_dt_ms": t_end / max(1, r["accepted"]),
+        "alu_tflops_wall": round(achieved, 3),
+        "frac_of_peak_wall": round(achieved / PEAK_TFLOPS[w.precision], 4),
+        "n_nonfinite": st["n_nonfinite"],
         "V": V,
     }
 
@@ -229,6 +285,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
+    ap.add_argument("--no-ros2", action="store_true")
+    ap.add_argument("--adaptive-tol", type=float, default=1e-3)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
     args = ap.parse_args()
@@ -256,8 +314,33 @@ def main():
         print("[bench] %s: %.3e vertex-steps/s, kernel %.1f ms" % (prec, res[prec]["value"],
               res[prec]["kernel_ms"]), file=sys.stderr, flush=True)
     Vf, Vm = res["fp64"].pop("V"), res["mixed"].pop("V")
-    mixed_err = {"max": float(np.max(np.abs(Vm - Vf)) / np.max(np.abs(Vf))),
-                 "rms": float(np.sqrt(np.mean((Vm - Vf) ** 2)) / np.max(np.abs(Vf)))}
+
+    def verr(V):
+        return {"max": float(np.max(np.abs(V - Vf)) / np.max(np.abs(Vf))),
+                "rms": float(np.sqrt(np.mean((V - Vf) ** 2)) / np.max(np.abs(Vf)))}
+
+    mixed_err = verr(Vm)
+
+    ros2 = None
+    if not args.no_ros2:
+        # the paper's own scheme: ROS2 predictor + one trapezoidal correction, over the
+        # same 10 ms of the same slab; V compared with the fp64 Newton run (3 nodes,
+        # 3 sweeps, order 4) at the end
+        ros2 = {"fixed": {}, "adaptive": {}}
+        for prec in ("mixed", "fp64"):
+            w = W.c2_tt06(precision=prec)
+            w.n_nodes, w.n_sweeps = 2, 1
+            print("[bench] ros2 fixed %s" % prec, file=sys.stderr, flush=True)
+            r = run_pass_set(I, torch, w, args.steps, args.warmup, predictor="ros2")
+            r["V_error_vs_fp64_newton"] = verr(r.pop("V"))
+            ros2["fixed"][prec] = {k: r[k] for k in ("value", "kernel_ms", "roofline",
+                                                     "V_error_vs_fp64_newton", "n_nonfinite")}
+        for prec in ("mixed", "fp64"):
+            w = W.c2_tt06(precision=prec)
+            print("[bench] ros2 adaptive %s" % prec, file=sys.stderr, flush=True)
+            a = run_adaptive(I, torch, w, args.adaptive_tol, w.n_steps * w.dt, 0.05)
+            a["V_error_vs_fp64_newton"] = verr(a.pop("V"))
+            ros2["adaptive"][prec] = a
 
     serving = None
     if not args.no_serving:
@@ -302,6 +385,7 @@ def main():
         "hbm_gbs_algorithmic": m["hbm_gbs_algorithmic"],
         "cpu_baseline": cpu,
         "serving": serving,
+        "ros2_sdc": ros2,
     }
     print(json.dumps(out))
 

@@ -7,10 +7,13 @@
  * diffusion current I_diff), every mesh vertex carries the state
  * X = (v, w, c) of equation genODE and integrates dX/dt = F(X) with M~ = I,
  *     F = [ -(I_ion + I_stim) + I_diff ; G(v, w) ; S(v, w, c) ]
- * (equations parabolic, odes_con, odes).  One time step runs a
- * backward-Euler local-Newton predictor over the M Gauss-Lobatto
- * sub-intervals and K linearised implicit corrections (equations residual,
- * sdc_ode, sdc; M = 2, K = 1 is the paper's trapezoidal correction).  The
+ * (equations parabolic, odes_con, odes).  One time step runs a predictor
+ * over the M Gauss-Lobatto sub-intervals -- backward Euler by local Newton,
+ * or the paper's Rosenbrock method ROS2 (section 3.3.1, equation
+ * rb_system) -- and K linearised implicit corrections (equations residual,
+ * sdc_ode, sdc; M = 2, K = 1 is the paper's trapezoidal correction).  With
+ * ROS2 the step size can also be chosen adaptively from its embedded
+ * solution (reaction_sdc_adaptive).  The
  * local Jacobian uses exact derivatives (text after equation rb_system) and a
  * sparsity fixed at compile time (the paper's CTSM technique).
  *
@@ -70,6 +73,14 @@ enum {
   IONIC_ESTATE = -5        /* handle used in a wrong state (e.g. mixed batch)   */
 };
 
+/* Predictor on each Gauss-Lobatto sub-interval.  IONIC_PRED_NEWTON:
+ * backward Euler Y - X_m - dtau F(Y) = 0 by local Newton (the first-order
+ * implicit integrator of the correction equation, section 3.3.2).
+ * IONIC_PRED_ROS2: one step of the two-stage, second-order, L-stable
+ * Rosenbrock method ROS2 (section 3.3.1, equation rb_system) with
+ * gamma = 1 + 1/sqrt(2), exact Jacobian, both stages on one factorisation. */
+enum { IONIC_PRED_NEWTON = 0, IONIC_PRED_ROS2 = 1 };
+
 #define IONIC_MAX_NODES 5   /* Gauss-Lobatto nodes per step: 2..5 */
 #define IONIC_MAX_SWEEPS 16 /* SDC corrections per step: 0..16   */
 
@@ -86,6 +97,18 @@ typedef struct {
   const double* params; /* host; overrides of the model's leading parameters, see
                            ionic_param_name(); NULL/0 = defaults */
 } ionic_config;
+
+/* Outcome of reaction_sdc_adaptive. */
+typedef struct {
+  double t;            /* time reached (ms); equals t_end when reached == 1       */
+  double dt_next;      /* step the controller proposes next                      */
+  double err_last;     /* scaled embedded error of the last attempt (inf: non-finite) */
+  int64_t accepted;    /* accepted attempts                                      */
+  int64_t rejected;    /* rejected attempts                                      */
+  int32_t reached;     /* 1 iff t_end was reached                                */
+  int32_t failed;      /* 1 iff the run stopped early: attempts exhausted, or the
+                          step fell below 1e-12 ms                               */
+} ionic_adapt_result;
 
 typedef struct {
   int64_t vertex_steps;      /* sum over launches of N * n_steps                  */
@@ -157,6 +180,42 @@ int reaction_sdc_step(ionic_sim* sim, double t0, double dt, int n_steps, int n_n
                       int n_sweeps, const double* i_stim_dev, double stim_t_on,
                       double stim_t_off, const double* i_diff_dev, void* hip_stream);
 
+/* Choose the predictor used by reaction_sdc_step and reaction_sdc_step_batch
+ * on this handle (default IONIC_PRED_NEWTON).  With IONIC_PRED_ROS2 the
+ * Newton settings of the config are unused and the Newton counters stay 0.
+ * Host only; takes effect for work enqueued afterwards. */
+int ionic_set_predictor(ionic_sim* sim, int predictor);
+
+/* Adaptive time stepping from t0 to t_end with the ROS2 predictor and
+ * n_sweeps corrections on n_nodes nodes (the paper's scheme: n_nodes = 2,
+ * n_sweeps = 1), one step size for all vertices (section 3.3.1: the embedded
+ * ROS2 solution chooses the next step; section 4: steps capped at dt_max).
+ * Per attempt with step tau from t:
+ *   err = max over vertices, sub-intervals and states of
+ *         |X_i - X_hat_i| / max(|X_i|, scale_i)   (X_hat: embedded solution,
+ *         scale_i: the per-state floor of the Newton stop);
+ *   accepted iff err <= err_tol (a non-finite state rejects);
+ *   next step tau * min(2, max(0.2, 0.9 sqrt(err_tol/err))), capped at dt_max.
+ * Steps never cross the breakpoints stim_t_on, stim_t_off and t_end: a step
+ * that would reach one is cut to end there exactly.  The stimulus is on for a
+ * step from t iff stim_t_on <= t + tau/2 < stim_t_off.  The controller runs on
+ * the device, so attempts queue without host round trips; the host checks
+ * progress between batches of attempts.
+ *  work_dev: caller-owned device buffer of >= ionic_state_bytes(...) bytes,
+ *            the second state buffer of accept/reject; on return the result
+ *            is in the handle's own state buffer.
+ *  max_attempts: >= 1, cap on accepted + rejected attempts.
+ *  history_dev: device array of 4 * max_attempts doubles or NULL; row a holds
+ *            (t, tau, err, accepted) of attempt a.
+ *  out: host; filled on return.
+ * t_end > t0, 0 < dt_init, 0 < dt_max, err_tol > 0, all finite.
+ * Synchronises hip_stream before returning. */
+int reaction_sdc_adaptive(ionic_sim* sim, double t0, double t_end, double dt_init, double dt_max,
+                          double err_tol, int n_nodes, int n_sweeps, const double* i_stim_dev,
+                          double stim_t_on, double stim_t_off, const double* i_diff_dev,
+                          void* work_dev, size_t work_bytes, int64_t max_attempts,
+                          double* history_dev, ionic_adapt_result* out, void* hip_stream);
+
 /* Store the step inputs of `sim` for reaction_sdc_step_batch (same meaning as
  * the arguments of reaction_sdc_step).  The batch advances the handle's own
  * step counter, so chunks of a long run keep t_n = t0 + n*dt exact. */
@@ -166,8 +225,8 @@ int ionic_set_inputs(ionic_sim* sim, double t0, double dt, int n_nodes, int n_sw
 
 /* Continuous-batching entry: advance n_sims handles by n_steps[i] steps each
  * in as few launches as possible (one per group of up to 24 handles).  All
- * handles must share model, precision, n_nodes, parameters and Newton
- * settings (else IONIC_ESTATE).  Each vertex computes exactly what a
+ * handles must share model, precision, predictor, n_nodes, parameters and
+ * Newton settings (else IONIC_ESTATE).  Each vertex computes exactly what a
  * reaction_sdc_step call on its own handle computes (bit-identical). */
 int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_sims,
                             void* hip_stream);

@@ -84,6 +84,7 @@ def advance_adaptive(model, X0, *, t0=0.0, t_end, dt_init, dt_max=0.05, err_tol,
     dt_try = min(float(dt_init), float(dt_max))
     while t < t_end:
         if len(st.history) >= max_attempts:
+            st.failed = True
             break
         b = next_breakpoint(t, stim_on, stim_off, t_end)
         hit = dt_try >= b - t
@@ -94,7 +95,7 @@ def advance_adaptive(model, X0, *, t0=0.0, t_end, dt_init, dt_max=0.05, err_tol,
         t_mid = t + 0.5 * tau
         stim = stim_amp if (stim_on <= t_mid < stim_off) else np.zeros(N)
         Xn, err_v = sdc_step(model, X, stim, tau, n_nodes, n_sweeps, diff, 0.0, 1, clamp_v,
-                             scratch, S * 1.0, c, predictor="ros2")
+                             scratch, S, c, predictor="ros2")
         err = float(np.max(err_v)) if np.all(np.isfinite(err_v)) else float("inf")
         ok = err <= err_tol
         st.history.append((t, tau, err, ok))

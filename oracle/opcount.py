@@ -181,6 +181,30 @@ def solve_flops(pattern, n_fp64):
     return flops, int(P.sum())
 
 
+def resolve_flops(pattern, n_fp64):
+    """Flops of a second right-hand side on a kept factorisation (ROS2 stage 2):
+    forward substitution with the multipliers and back substitution on the
+    filled pattern, gates first as in solve_flops."""
+    n = len(pattern)
+    P = np.zeros((n, n), dtype=bool)
+    for i, row in enumerate(pattern):
+        P[i, row] = True
+        P[i, i] = True
+    order = list(range(n_fp64, n)) + list(range(n_fp64))
+    flops = 0
+    for k, p in enumerate(order):
+        later = order[k + 1:]
+        for i in later:
+            if P[i, p]:
+                for j in later:
+                    if P[p, j]:
+                        P[i, j] = True
+                flops += 2                          # b_i -= l b_p
+    for k, p in enumerate(order):
+        flops += 2 * int(sum(P[p, j] for j in order[k + 1:])) + 1
+    return flops
+
+
 def flops(c):
     return sum(c.get(k, 0) for k in FLOP_KINDS)
 
@@ -190,7 +214,8 @@ def per_evaluation(model, x, n_fp64):
     cFJ, pattern = count_eval(model, x, True)
     sf, nnz = solve_flops(pattern, n_fp64)
     return {
-        "F": flops(cF), "FJ": flops(cFJ), "solve": sf, "nnz": sum(len(r) for r in pattern),
+        "F": flops(cF), "FJ": flops(cFJ), "solve": sf, "resolve": resolve_flops(pattern, n_fp64),
+        "nnz": sum(len(r) for r in pattern),
         "nnz_filled": nnz,
         "transcendental_F": sum(cF.get(k, 0) for k in ("exp", "log", "sqrt", "expm1")),
         "div_F": cF.get("div", 0),
@@ -210,6 +235,18 @@ def flops_per_launch(ev, n, n_steps, M, K, newton_iters):
             + newton_iters * 6 * n
             # sweep: quadrature (2 flops per term), residual (2) and update (1) per state
             + n_steps * K * ((M - 1) * M * 2 + (M - 1) * 3) * n)
+
+
+def flops_per_launch_ros2(ev, n, n_steps, M, K):
+    """Algorithmic flops of one launch with the ROS2 predictor: per sub-interval
+    one F+J evaluation with its elimination, one F evaluation and one second
+    solve, plus the stage arithmetic per state (stage-1 right-hand side 1, stage
+    point 2, stage-2 right-hand side 2, update 4, error estimate 3); the sweeps
+    as with the Newton predictor except that F(X_n) comes from the first stage."""
+    per_sub = ev["FJ"] + ev["solve"] + ev["F"] + ev["resolve"] + 12 * n
+    sweeps = (K * (M - 2) * ev["F"] + K * (M - 1) * (ev["FJ"] + ev["solve"])
+              + K * ((M - 1) * M * 2 + (M - 1) * 3) * n)
+    return n_steps * ((M - 1) * per_sub + sweeps)
 
 
 if __name__ == "__main__":

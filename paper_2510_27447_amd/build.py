@@ -2,7 +2,9 @@
 
 Every HIP translation unit is compiled with packed-FP32 instructions
 disabled (-Xclang -target-feature -Xclang -packed-fp32-ops); the model
-kernels compile in parallel, then hipcc links the shared library.
+kernels compile in parallel, then hipcc links the shared library.  The device
+assembly of every unit is checked for a known miscompilation (spill code ahead
+of an execution-mask restore, codegen_check.py) before linking.
 """
 from __future__ import annotations
 
@@ -10,6 +12,11 @@ import os
 import subprocess
 import sys
 from concurrent.futures import ThreadPoolExecutor
+
+try:
+    from . import codegen_check
+except ImportError:  # run as a script
+    import codegen_check
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -20,17 +27,21 @@ OBJDIR = os.path.join(LIBDIR, "obj")
 LIBNAME = "libionic_sdc.so"
 LIBPATH = os.path.join(LIBDIR, LIBNAME)
 
-SOURCES = ["kernels_tt06_fp64.hip", "kernels_tt06.hip", "kernels_lr91_fp64.hip",
-           "kernels_lr91.hip", "kernels_test.hip", "ionic.cpp"]
+STEP_FP64 = ["kernels_tt06_fp64.hip", "kernels_tt06_fp64_ros2.hip", "kernels_lr91_fp64.hip",
+             "kernels_lr91_fp64_ros2.hip"]
+STEP_MIXED = ["kernels_tt06_mixed.hip", "kernels_tt06_mixed_ros2.hip", "kernels_lr91_mixed.hip",
+              "kernels_lr91_mixed_ros2.hip"]
+# slowest first, so the parallel build ends sooner
+SOURCES = STEP_FP64 + STEP_MIXED + ["kernels_tt06.hip", "kernels_lr91.hip", "kernels_test.hip",
+                                    "control.hip", "ionic.cpp"]
 # per-source optimisation level (default -O3); the double-precision step
 # kernels of the cell models are built at -O1, where their code is exact
 # (see the headers of those files)
-OPT = {"kernels_tt06_fp64.hip": "-O1", "kernels_lr91_fp64.hip": "-O1"}
+OPT = {s: "-O1" for s in STEP_FP64}
 # the mixed-precision step kernels may reassociate fp arithmetic (NaN/Inf
 # semantics kept, so non-finite states are still detected); results move at
 # the rounding level only, far below the mixed path's tolerance
-EXTRA = {s: ["-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"]
-         for s in ("kernels_tt06.hip", "kernels_lr91.hip")}
+EXTRA = {s: ["-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"] for s in STEP_MIXED}
 ARCH = os.environ.get("IONIC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH, "-std=c++20", "-fPIC",
@@ -47,16 +58,29 @@ def _hipcc():
 
 
 def _compile(src, extra):
-    obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
+    stem = os.path.splitext(src)[0]
+    obj = os.path.join(OBJDIR, stem + ".o")
+    # -save-temps keeps the device assembly of this very compile for the check below
     cmd = ([_hipcc(), "-x", "hip", OPT.get(src, "-O3")] + FLAGS + EXTRA.get(src, []) + extra
-           + ["-c", os.path.join(CSRC, src), "-o", obj])
-    r = subprocess.run(cmd, capture_output=True, text=True)
+           + ["-save-temps=obj", "-c", os.path.join(CSRC, src), "-o", obj])
+    r = subprocess.run(cmd, capture_output=True, text=True, cwd=OBJDIR)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s" % (" ".join(cmd), r.stderr[-6000:]))
+    if src.endswith(".hip"):
+        asm = os.path.join(OBJDIR, "%s-hip-amdgcn-amd-amdhsa-%s.s" % (stem, ARCH))
+        if not os.path.exists(asm):
+            raise RuntimeError("device assembly of %s not found at %s" % (src, asm))
+        found = codegen_check.check_file(asm)
+        if found:
+            lines = "\n".join("  %s %s line %d: %s" % f for f in found[:20])
+            raise RuntimeError(
+                "%s: %d lane-masked vector writes placed before the execution-mask restore of "
+                "a divergent join (a miscompilation that loses values of masked lanes):\n%s"
+                % (src, len(found), lines))
     return obj
 
 
-def build(jobs: int = 6, extra_flags=(), verbose: bool = True) -> str:
+def build(jobs: int = 8, extra_flags=(), verbose: bool = True) -> str:
     """Compile every source and link the shared library; returns its path."""
     os.makedirs(OBJDIR, exist_ok=True)
     extra = list(extra_flags)

@@ -69,6 +69,17 @@ IONIC_DEV float f_log(float x) { return __logf(x); }
 IONIC_DEV float f_sqrt(float x) { return __builtin_sqrtf(x); }
 IONIC_DEV float f_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Per-lane choice between two values that are both computed.  Written as a
+// call, its arguments are evaluated before it, so the optimiser is left with a
+// select; a conditional expression with a longer alternative is otherwise
+// emitted as a branch around that alternative, which on the GPU is a divergent
+// branch.  The step kernels keep no divergent branches in their per-step work
+// (see sdc_kernel.h).
+template <class T>
+IONIC_DEV T pick(bool c, T a, T b) {
+  return c ? a : b;
+}
+
 // ---- the dual type ------------------------------------------------------------
 template <class T, uint32_t M>
 struct D {
@@ -249,9 +260,9 @@ IONIC_DEV D<T, A> sq(const D<T, A>& a) {
 template <class T, uint32_t A, uint32_t B>
 IONIC_DEV D<T, A | B> select(bool cond, const D<T, A>& a, const D<T, B>& b) {
   D<T, A | B> r;
-  r.v = cond ? a.v : b.v;
-  combine(r, a, b, [&](T x) { return cond ? x : T(0); }, [&](T y) { return cond ? T(0) : y; },
-          [&](T x, T y) { return cond ? x : y; });
+  r.v = pick(cond, a.v, b.v);
+  combine(r, a, b, [&](T x) { return pick(cond, x, T(0)); },
+          [&](T y) { return pick(cond, T(0), y); }, [&](T x, T y) { return pick(cond, x, y); });
   return r;
 }
 
@@ -259,13 +270,13 @@ IONIC_DEV D<T, A | B> select(bool cond, const D<T, A>& a, const D<T, B>& b) {
 template <class T, uint32_t A>
 IONIC_DEV D<T, A> x_over_1mexp(const D<T, A>& x, double a) {
   const bool zero = (x.v == T(0));
-  const T xs = zero ? T(1) : x.v;
+  const T xs = pick(zero, T(1), x.v);
   const T em = f_expm1(T(-a) * xs);  // exp(-a x) - 1
   const T den = -em;
   const T inv = f_rcp(den);
-  const T val = zero ? T(1.0 / a) : xs * inv;
+  const T val = pick(zero, T(1.0 / a), xs * inv);
   // d/dx [x / (1 - e^{-ax})] = (den - a x e^{-ax}) / den^2
-  const T slope = zero ? T(0.5) : (den - T(a) * xs * (em + T(1))) * inv * inv;
+  const T slope = pick(zero, T(0.5), (den - T(a) * xs * (em + T(1))) * inv * inv);
   return map_partials(x, val, [&](T g) { return slope * g; });
 }
 
@@ -273,12 +284,12 @@ IONIC_DEV D<T, A> x_over_1mexp(const D<T, A>& x, double a) {
 template <class T, uint32_t A>
 IONIC_DEV D<T, A> expm1_over_x(const D<T, A>& x, double a) {
   const bool zero = (x.v == T(0));
-  const T xs = zero ? T(1) : x.v;
+  const T xs = pick(zero, T(1), x.v);
   const T em = f_expm1(T(a) * xs);
   const T inv = f_rcp(xs);
-  const T val = zero ? T(a) : em * inv;
+  const T val = pick(zero, T(a), em * inv);
   // d/dx [(e^{ax} - 1)/x] = (a x e^{ax} - (e^{ax} - 1)) / x^2
-  const T slope = zero ? T(0.5 * a * a) : (T(a) * xs * (em + T(1)) - em) * inv * inv;
+  const T slope = pick(zero, T(0.5 * a * a), (T(a) * xs * (em + T(1)) - em) * inv * inv);
   return map_partials(x, val, [&](T g) { return slope * g; });
 }
 
@@ -286,12 +297,12 @@ IONIC_DEV D<T, A> expm1_over_x(const D<T, A>& x, double a) {
 template <class T, uint32_t A>
 IONIC_DEV D<T, A> u_over_expm1_2u(const D<T, A>& u) {
   const bool zero = (u.v == T(0));
-  const T us = zero ? T(1) : u.v;
+  const T us = pick(zero, T(1), u.v);
   const T em = f_expm1(T(2) * us);
   const T inv = f_rcp(em);
-  const T val = zero ? T(0.5) : us * inv;
+  const T val = pick(zero, T(0.5), us * inv);
   // d/du [u / (e^{2u} - 1)] = (em - 2u e^{2u}) / em^2
-  const T slope = zero ? T(-0.5) : (em - T(2) * us * (em + T(1))) * inv * inv;
+  const T slope = pick(zero, T(-0.5), (em - T(2) * us * (em + T(1))) * inv * inv);
   return map_partials(u, val, [&](T g) { return slope * g; });
 }
 

@@ -14,7 +14,10 @@
 #include "ionic_sdc.h"
 #include "kernel_ops.h"
 
+using ionic::AdaptCtl;
 using ionic::DevStats;
+using ionic::ErrSlot;
+using ionic::kSlots;
 using ionic::kBlock;
 using ionic::kMaxBatch;
 using ionic::kMaxNodes;
@@ -106,6 +109,13 @@ void lobatto_matrix(int M, const double* c, double* S /* (M-1) x M */) {
   }
 }
 
+// library-owned device memory of one handle
+struct DevBlock {
+  DevStats stats[kSlots];
+  ErrSlot err[kSlots];
+  AdaptCtl ctl;
+};
+
 }  // namespace
 
 struct ionic_sim {
@@ -120,6 +130,8 @@ struct ionic_sim {
   alignas(16) unsigned char p32[1024];
   double tol = 0.0;
   int maxit = 0;
+  int predictor = IONIC_PRED_NEWTON;
+  DevBlock* dev = nullptr;  // statistics slots and the adaptive control block
   DevStats* stats = nullptr;
   // inputs for the batched entry
   bool inputs_set = false;
@@ -270,16 +282,17 @@ int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   auto cleanup = [&](int rc) {
-    if (s->stats) (void)hipFree(s->stats);
+    if (s->dev) (void)hipFree(s->dev);
     delete s;
     return rc;
   };
-  hipError_t e = hipMalloc(&s->stats, sizeof(DevStats));
+  hipError_t e = hipMalloc(&s->dev, sizeof(DevBlock));
   if (e != hipSuccess) {
-    s->stats = nullptr;
+    s->dev = nullptr;
     return cleanup(hip_fail(e, "hipMalloc(stats)"));
   }
-  e = hipMemsetAsync(s->stats, 0, sizeof(DevStats), st);
+  s->stats = s->dev->stats;
+  e = hipMemsetAsync(s->dev, 0, sizeof(DevBlock), st);
   if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemsetAsync(stats)"));
 
   const double* src = x0;
@@ -306,7 +319,7 @@ int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t
 void ionic_destroy(ionic_sim* s) {
   if (!s) return;
   (void)hipDeviceSynchronize();
-  if (s->stats) (void)hipFree(s->stats);
+  if (s->dev) (void)hipFree(s->dev);
   delete s;
 }
 
@@ -325,9 +338,89 @@ int reaction_sdc_step(ionic_sim* s, double t0, double dt, int n_steps, int n_nod
   c.sims[0] = desc_of(s, t0, dt, i_stim_dev, stim_t_on, stim_t_off, i_diff_dev, 0, n_steps,
                       n_sweeps, 0);
   const int blocks = int((s->n + kBlock - 1) / kBlock);
-  hipError_t e = (s->precision == IONIC_FP64 ? s->ops->sdc64 : s->ops->sdc32)(
-      n_nodes, s->params(), c, blocks, static_cast<hipStream_t>(hip_stream));
+  hipError_t e = s->ops->sdc[s->precision][s->predictor](n_nodes, s->params(), c, blocks,
+                                                         static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel");
+  return IONIC_OK;
+}
+
+int ionic_set_predictor(ionic_sim* s, int predictor) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (predictor != IONIC_PRED_NEWTON && predictor != IONIC_PRED_ROS2)
+    return fail(IONIC_EUNSUPPORTED, "unknown predictor " + std::to_string(predictor));
+  s->predictor = predictor;
+  return IONIC_OK;
+}
+
+int reaction_sdc_adaptive(ionic_sim* s, double t0, double t_end, double dt_init, double dt_max,
+                          double err_tol, int n_nodes, int n_sweeps, const double* i_stim_dev,
+                          double stim_t_on, double stim_t_off, const double* i_diff_dev,
+                          void* work_dev, size_t work_bytes, int64_t max_attempts,
+                          double* history_dev, ionic_adapt_result* out, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (!out) return fail(IONIC_EINVAL, "out is NULL");
+  int rc = check_step_args(t0, 1.0, 0, n_nodes, n_sweeps, stim_t_on, stim_t_off);
+  if (rc != IONIC_OK) return rc;
+  if (!std::isfinite(t_end) || !(t_end > t0)) return fail(IONIC_EINVAL, "t_end must be finite and > t0");
+  if (!(dt_init > 0.0) || !std::isfinite(dt_init)) return fail(IONIC_EINVAL, "dt_init must be positive and finite");
+  if (!(dt_max > 0.0) || !std::isfinite(dt_max)) return fail(IONIC_EINVAL, "dt_max must be positive and finite");
+  if (!(err_tol > 0.0) || !std::isfinite(err_tol)) return fail(IONIC_EINVAL, "err_tol must be positive and finite");
+  if (max_attempts < 1) return fail(IONIC_EINVAL, "max_attempts must be >= 1");
+  if (!work_dev) return fail(IONIC_EINVAL, "work_dev is NULL");
+  const size_t need = bytes_of(s->ops, s->precision, s->n);
+  if (work_bytes < need)
+    return fail(IONIC_EINVAL, "work buffer too small: need " + std::to_string(need) + " bytes");
+  if (work_dev == s->state) return fail(IONIC_EINVAL, "work_dev must differ from the state buffer");
+
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  constexpr double kDtMin = 1e-12;
+  AdaptCtl* ctl = &s->dev->ctl;
+  ErrSlot* err = s->dev->err;
+  IONIC_HIP(ionic::adapt_init(ctl, err, t0, t_end, dt_init, dt_max, err_tol, kDtMin, stim_t_on,
+                              stim_t_off, (long long)max_attempts, st));
+  LaunchCommon c;
+  fill_quadrature(n_nodes, c);
+  c.tol = s->tol;
+  c.maxit = s->maxit;
+  c.n_sims = 1;
+  c.ctl = ctl;
+  c.err = err;
+  c.state_alt = work_dev;
+  // one step per attempt; t0, dt and the buffers come from the control block
+  c.sims[0] = desc_of(s, t0, 1.0, i_stim_dev, stim_t_on, stim_t_off, i_diff_dev, 0, 1, n_sweeps, 0);
+  const int blocks = int((s->n + kBlock - 1) / kBlock);
+  const ionic::SdcLaunch launch = s->ops->sdc[s->precision][IONIC_PRED_ROS2];
+
+  AdaptCtl h;
+  std::memset(&h, 0, sizeof(h));
+  h.t = t0;
+  h.dt_try = std::min(dt_init, dt_max);
+  int64_t enqueued = 0;
+  for (;;) {
+    // enough attempts to reach t_end at the current step, plus room for rejections
+    const double est = std::ceil((t_end - h.t) / std::max(h.dt_try, kDtMin));
+    int64_t chunk = int64_t(std::min(est, 4096.0)) + 8;
+    chunk = std::min<int64_t>(chunk, max_attempts - enqueued);
+    for (int64_t a = 0; a < chunk; ++a) {
+      hipError_t e = launch(n_nodes, s->params(), c, blocks, st);
+      if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (adaptive)");
+      IONIC_HIP(ionic::adapt_control(ctl, err, history_dev, (long long)max_attempts, st));
+    }
+    enqueued += chunk;
+    IONIC_HIP(hipMemcpyAsync(&h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
+    IONIC_HIP(hipStreamSynchronize(st));
+    if (h.done || enqueued >= max_attempts) break;
+  }
+  if (h.cur == 1)  // the last accepted state sits in the work buffer
+    IONIC_HIP(hipMemcpyAsync(s->state, work_dev, need, hipMemcpyDeviceToDevice, st));
+  IONIC_HIP(hipStreamSynchronize(st));
+  out->t = h.t;
+  out->dt_next = h.dt_try;
+  out->err_last = h.err_last;
+  out->accepted = h.accepted;
+  out->rejected = h.rejected;
+  out->reached = h.t >= t_end ? 1 : 0;
+  out->failed = h.failed || !(h.t >= t_end) ? 1 : 0;
   return IONIC_OK;
 }
 
@@ -364,9 +457,10 @@ int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_si
     if (!s->inputs_set)
       return fail(IONIC_ESTATE, "sims[" + std::to_string(i) + "]: ionic_set_inputs not called");
     if (s->model != s0->model || s->precision != s0->precision || s->M != s0->M ||
-        s->tol != s0->tol || s->maxit != s0->maxit || s->raw != s0->raw)
-      return fail(IONIC_ESTATE, "batched handles must share model, precision, n_nodes, "
-                                "parameters and Newton settings");
+        s->predictor != s0->predictor || s->tol != s0->tol || s->maxit != s0->maxit ||
+        s->raw != s0->raw)
+      return fail(IONIC_ESTATE, "batched handles must share model, precision, predictor, "
+                                "n_nodes, parameters and Newton settings");
     for (int k = 0; k < i; ++k)
       if (sims[k] == s) return fail(IONIC_EINVAL, "a handle appears twice in the batch");
   }
@@ -388,8 +482,7 @@ int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_si
     }
     if (cnt == 0) continue;
     c.n_sims = cnt;
-    hipError_t e = (s0->precision == IONIC_FP64 ? s0->ops->sdc64 : s0->ops->sdc32)(
-        s0->M, s0->params(), c, blocks, st);
+    hipError_t e = s0->ops->sdc[s0->precision][s0->predictor](s0->M, s0->params(), c, blocks, st);
     if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (batch)");
   }
   for (int k = 0; k < n_sims; ++k) sims[k]->step_offset += n_steps[k];
@@ -430,23 +523,25 @@ int ionic_gates_to_steady_state(ionic_sim* s, void* hip_stream) {
 int ionic_get_stats(ionic_sim* s, ionic_stats* out) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
   if (!out) return fail(IONIC_EINVAL, "out is NULL");
-  DevStats d;
+  std::vector<DevStats> d(kSlots);
   IONIC_HIP(hipDeviceSynchronize());
-  IONIC_HIP(hipMemcpy(&d, s->stats, sizeof(d), hipMemcpyDeviceToHost));
-  out->vertex_steps = int64_t(d.vertex_steps);
-  out->newton_iters = int64_t(d.newton_iters);
-  out->newton_solves = int64_t(d.newton_solves);
-  out->n_nonconverged = int64_t(d.nonconverged);
-  out->n_nonfinite = int64_t(d.nonfinite);
-  out->newton_it_max = int32_t(d.it_max);
-  out->reserved = 0;
+  IONIC_HIP(hipMemcpy(d.data(), s->stats, sizeof(DevStats) * kSlots, hipMemcpyDeviceToHost));
+  std::memset(out, 0, sizeof(*out));
+  for (const DevStats& x : d) {  // fold the slots
+    out->vertex_steps += int64_t(x.vertex_steps);
+    out->newton_iters += int64_t(x.newton_iters);
+    out->newton_solves += int64_t(x.newton_solves);
+    out->n_nonconverged += int64_t(x.nonconverged);
+    out->n_nonfinite += int64_t(x.nonfinite);
+    out->newton_it_max = std::max(out->newton_it_max, int32_t(x.it_max));
+  }
   return IONIC_OK;
 }
 
 int ionic_reset_stats(ionic_sim* s) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
   IONIC_HIP(hipDeviceSynchronize());
-  IONIC_HIP(hipMemset(s->stats, 0, sizeof(DevStats)));
+  IONIC_HIP(hipMemset(s->stats, 0, sizeof(DevStats) * kSlots));
   IONIC_HIP(hipDeviceSynchronize());
   return IONIC_OK;
 }

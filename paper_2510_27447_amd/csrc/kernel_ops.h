@@ -15,8 +15,14 @@ struct LaunchCommon {
   double tol;
   int maxit;
   int n_sims;
+  AdaptCtl* ctl;
+  ErrSlot* err;
+  void* state_alt;
   SimDesc sims[kMaxBatch];
 };
+
+using SdcLaunch = hipError_t (*)(int M, const void* params, const LaunchCommon& c, int blocks,
+                                 hipStream_t st);
 
 struct ModelOps {
   int n_states;
@@ -28,9 +34,8 @@ struct ModelOps {
   const char* const* state_names;
   size_t params_bytes[2];        // sizeof(Params<double>), sizeof(Params<float>)
   void (*derive)(const double* raw, void* p64, void* p32);
-  // fused step kernel, double / mixed precision policy
-  hipError_t (*sdc64)(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
-  hipError_t (*sdc32)(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
+  // fused step kernels, [precision policy: double, mixed][predictor: Newton, ROS2]
+  SdcLaunch sdc[2][2];
   hipError_t (*pack)(int prec, const double* src, long long ld, void* state, long long stride,
                      long long first, long long count, hipStream_t st);
   hipError_t (*unpack)(int prec, const void* state, long long stride, long long first,
@@ -41,11 +46,25 @@ struct ModelOps {
                           long long v, double stim, double diff, double* out, hipStream_t st);
 };
 
-// The double-precision step kernels of the cell models live in translation
-// units of their own, compiled at a lower optimisation level (see the build
-// script and kernels_fp64.hip).
-hipError_t tt06_sdc64(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
-hipError_t lr91_sdc64(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st);
+// The step kernels of the cell models live in translation units of their own
+// (one per model, precision policy and predictor) so they compile in
+// parallel; the double-precision ones are compiled at a lower optimisation
+// level (see the build script and kernels_*_fp64.hip).
+hipError_t tt06_sdc_fp64_newton(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t tt06_sdc_fp64_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t tt06_sdc_mixed_newton(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t tt06_sdc_mixed_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t lr91_sdc_fp64_newton(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t lr91_sdc_fp64_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t lr91_sdc_mixed_newton(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t lr91_sdc_mixed_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
+
+// Adaptive step control (control.hip).
+hipError_t adapt_init(AdaptCtl* c, ErrSlot* err, double t0, double t_end, double dt_init,
+                      double dt_max, double tol, double dt_min, double t_on, double t_off,
+                      long long max_attempts, hipStream_t st);
+hipError_t adapt_control(AdaptCtl* c, ErrSlot* err, double* history, long long history_len,
+                         hipStream_t st);
 
 extern const ModelOps kOpsLR91;
 extern const ModelOps kOpsTT06;

@@ -14,7 +14,7 @@ struct OpsImpl {
     *static_cast<typename Model::template Params<float>*>(p32) = Model::template derive<float>(raw);
   }
 
-  template <class Prec, int M>
+  template <class Prec, int Pred, int M>
   static hipError_t launch_m(const void* params, const LaunchCommon& c, int blocks, hipStream_t st) {
     using P = typename Model::template Params<typename Prec::TE>;
     LaunchArgs<P> a;
@@ -26,30 +26,26 @@ struct OpsImpl {
     a.tol = c.tol;
     a.maxit = c.maxit;
     a.n_sims = c.n_sims;
+    a.ctl = c.ctl;
+    a.err = c.err;
+    a.state_alt = c.state_alt;
     for (int s = 0; s < kMaxBatch; ++s) a.sims[s] = c.sims[s];
     static_assert(sizeof(LaunchArgs<P>) <= 3800, "kernel arguments must fit the kernarg segment");
-    hipLaunchKernelGGL((sdc_kernel<Model, Prec, M>), dim3(blocks), dim3(kBlock), 0, st, a);
+    hipLaunchKernelGGL((sdc_kernel<Model, Prec, M, Pred>), dim3(blocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
   }
 
-  template <class Prec>
-  static hipError_t sdc_prec(int M, const void* params, const LaunchCommon& c, int blocks,
-                             hipStream_t st) {
+  // node count dispatch of one (precision policy, predictor) pair
+  template <class Prec, int Pred>
+  static hipError_t sdc(int M, const void* params, const LaunchCommon& c, int blocks,
+                        hipStream_t st) {
     switch (M) {
-      case 2: return launch_m<Prec, 2>(params, c, blocks, st);
-      case 3: return launch_m<Prec, 3>(params, c, blocks, st);
-      case 4: return launch_m<Prec, 4>(params, c, blocks, st);
-      case 5: return launch_m<Prec, 5>(params, c, blocks, st);
+      case 2: return launch_m<Prec, Pred, 2>(params, c, blocks, st);
+      case 3: return launch_m<Prec, Pred, 3>(params, c, blocks, st);
+      case 4: return launch_m<Prec, Pred, 4>(params, c, blocks, st);
+      case 5: return launch_m<Prec, Pred, 5>(params, c, blocks, st);
       default: return hipErrorInvalidValue;
     }
-  }
-  static hipError_t sdc64(int M, const void* params, const LaunchCommon& c, int blocks,
-                          hipStream_t st) {
-    return sdc_prec<Fp64>(M, params, c, blocks, st);
-  }
-  static hipError_t sdc32(int M, const void* params, const LaunchCommon& c, int blocks,
-                          hipStream_t st) {
-    return sdc_prec<Mixed>(M, params, c, blocks, st);
   }
 
   static int grid(long long count) { return int((count + kAuxBlock - 1) / kAuxBlock); }
@@ -103,9 +99,9 @@ struct OpsImpl {
     return int(sizeof(Model::PARAM_DEFAULTS) / sizeof(double));
   }
 
-  // with_fp64 = false leaves sdc64 unset (the caller installs a launcher from
-  // another translation unit) so the double kernels are not instantiated here
-  template <bool with_fp64 = true>
+  // with_step = false leaves the step kernels unset (the caller installs
+  // launchers from other translation units), so none is instantiated here
+  template <bool with_step = true>
   static ModelOps make(const char* const* state_names) {
     ModelOps o{};
     o.n_states = Model::N;
@@ -118,8 +114,12 @@ struct OpsImpl {
     o.params_bytes[0] = sizeof(typename Model::template Params<double>);
     o.params_bytes[1] = sizeof(typename Model::template Params<float>);
     o.derive = &derive;
-    if constexpr (with_fp64) o.sdc64 = &sdc64;
-    o.sdc32 = &sdc32;
+    if constexpr (with_step) {
+      o.sdc[0][kPredNewton] = &sdc<Fp64, kPredNewton>;
+      o.sdc[0][kPredRos2] = &sdc<Fp64, kPredRos2>;
+      o.sdc[1][kPredNewton] = &sdc<Mixed, kPredNewton>;
+      o.sdc[1][kPredRos2] = &sdc<Mixed, kPredRos2>;
+    }
     o.pack = &pack;
     o.unpack = &unpack;
     o.steady = &steady;

@@ -1,4 +1,5 @@
-// TT06 (epicardial) instantiations of the reaction + SDC kernels.
+// TT06 (epicardial) launch table and auxiliary kernels; the step kernels are
+// instantiated in kernels_tt06_{fp64,mixed}[_ros2].hip.
 #include "kernel_ops_impl.h"
 #include "model_tt06.h"
 
@@ -8,7 +9,10 @@ static const char* const kNamesTT06[] = {"V",   "Cai", "CaSR", "CaSS", "Nai", "K
                                          "d",   "f",   "f2",   "fCass", "Rbar"};
 static ModelOps make_tt06() {
   ModelOps o = OpsImpl<TT06>::make<false>(kNamesTT06);
-  o.sdc64 = &tt06_sdc64;  // instantiated in kernels_tt06_fp64.hip
+  o.sdc[0][kPredNewton] = &tt06_sdc_fp64_newton;
+  o.sdc[0][kPredRos2] = &tt06_sdc_fp64_ros2;
+  o.sdc[1][kPredNewton] = &tt06_sdc_mixed_newton;
+  o.sdc[1][kPredRos2] = &tt06_sdc_mixed_ros2;
   return o;
 }
 const ModelOps kOpsTT06 = make_tt06();

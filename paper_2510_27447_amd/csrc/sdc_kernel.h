@@ -2,11 +2,17 @@
 // picard_form, residual, sdc_ode, sdc), one vertex per lane.
 //
 // Per time step and vertex, entirely in registers:
-//   predictor   X_0 = X_n; for each Gauss-Lobatto sub-interval m, backward
-//               Euler Y - X_m - dtau_m F(Y) = 0 by local Newton with the exact
-//               sparse Jacobian; the lane stops when
+//   predictor   X_0 = X_n; on each Gauss-Lobatto sub-interval m either
+//               (Newton) backward Euler Y - X_m - dtau_m F(Y) = 0 by local
+//               Newton with the exact sparse Jacobian; the lane stops when
 //               max_i |delta_i| / max(|Y_i|, scale_i) <= tol (>= 1 iteration,
-//               <= maxit); the wave runs until its last lane stops;
+//               <= maxit); the wave runs until its last lane stops; or
+//               (ROS2) one step of the two-stage Rosenbrock method of
+//               section 3.3.1 (equation rb_system, gamma = 1 + 1/sqrt(2)):
+//               one F+J evaluation and elimination at X_m, one F evaluation at
+//               X_m + k_1/gamma and a second solve with the kept
+//               factorisation; the embedded solution X_m + k_1/gamma gives the
+//               scaled error estimate used for step-size control;
 //   corrections K times: F at every node, quadrature Q_m = sum_j S_mj dt F_j,
 //               then node by node r = X^{k+1}_m - X^k_{m+1} + Q_m and
 //               (I - dtau_m J(X^k_{m+1})) delta = r, X^{k+1}_{m+1} += delta
@@ -33,10 +39,30 @@
 namespace ionic {
 
 constexpr int kMaxNodes = 5;
+constexpr int kPredNewton = 0;
+constexpr int kPredRos2 = 1;
+
+// ROS2 coefficients in the form of equation rb_system multiplied through by
+// tau * gamma:  (I - gamma tau J) k_1 = gamma tau F(X),
+//               (I - gamma tau J) k_2 = gamma tau F(X + k_1 / gamma) - 2 k_1,
+//               X_new = X + 3/(2 gamma) k_1 + 1/(2 gamma) k_2,
+//               X_hat = X + k_1 / gamma,  X_new - X_hat = (k_1 + k_2) / (2 gamma).
+constexpr double kRosGamma = 1.70710678118654752440;  // 1 + 1/sqrt(2)
+constexpr double kRosA21 = 0.58578643762690495120;    // 1/gamma = 2 - sqrt(2)
+constexpr double kRosM1 = 0.87867965644035742680;     // 3/(2 gamma)
+constexpr double kRosM2 = 0.29289321881345247560;     // 1/(2 gamma)
 constexpr int kMaxBatch = 24;
 constexpr int kBlock = 64;  // one wavefront per workgroup
 
-struct DevStats {
+// Statistics and the adaptive error maximum are reduced per wave and then
+// added atomically into one of kSlots cache-line slots, slot = workgroup mod
+// kSlots.  Workgroups are dealt to the XCDs round robin, so each slot is only
+// touched from one XCD, and no single address takes one atomic per wave (on a
+// 1e6-vertex launch that is 15,625 waves, which serialised on one address
+// cost about a millisecond).  The host and the control kernel fold the slots.
+constexpr int kSlots = 64;
+
+struct alignas(128) DevStats {
   unsigned long long vertex_steps;
   unsigned long long newton_iters;
   unsigned long long newton_solves;
@@ -44,6 +70,26 @@ struct DevStats {
   unsigned long long nonfinite;
   unsigned int it_max;
   unsigned int pad;
+};
+
+// Largest scaled error of the lanes of one slot, as the bits of a double >= 0
+// (the bit patterns of non-negative doubles order like the values).
+struct alignas(128) ErrSlot {
+  unsigned long long bits;
+};
+
+// Step-size control block of one adaptive run (one simulation per launch).
+// The step kernel reads the pending attempt (t, tau, which buffer holds the
+// state) and raises its error slot to the largest lane error; the control
+// kernel then folds the slots, accepts or rejects the attempt and plans the
+// next one.
+struct AdaptCtl {
+  double t, tau, dt_try, b;     // time, step of the pending attempt, proposed step, its breakpoint
+  double t_end, dt_max, tol, dt_min, t_on, t_off;
+  double err_last;
+  long long accepted, rejected, attempts, max_attempts;
+  int cur;                      // 0: the state is in the simulation's buffer, 1: in the work buffer
+  int done, failed, hit;
 };
 
 struct SimDesc {
@@ -55,7 +101,7 @@ struct SimDesc {
   double t0, dt, t_on, t_off;
   long long step_offset;   // steps already taken from t0
   int n_steps, n_sweeps;
-  DevStats* stats;
+  DevStats* stats;         // kSlots slots
   int first_block;         // first workgroup of this simulation in the launch
   int pad;
 };
@@ -68,6 +114,9 @@ struct LaunchArgs {
   double tol;
   int maxit;
   int n_sims;
+  AdaptCtl* ctl;     // adaptive run (ROS2 kernels, one simulation) or null
+  ErrSlot* err;      // adaptive run: kSlots error slots
+  void* state_alt;   // adaptive run: the second state buffer
   SimDesc sims[kMaxBatch];
 };
 
@@ -202,7 +251,15 @@ IONIC_DEV unsigned int wave_max(unsigned int x) {
   return x;
 }
 
-template <class Model, class Prec, int M>
+IONIC_DEV unsigned long long wave_max_u64(unsigned long long x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(x, o, 64);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+template <class Model, class Prec, int M, int Pred>
 __global__ void __launch_bounds__(kBlock)
     sdc_kernel(const LaunchArgs<typename Model::template Params<typename Prec::TE>> args) {
   using L = Layout<Model, Prec>;
@@ -219,10 +276,25 @@ __global__ void __launch_bounds__(kBlock)
   const bool active = v < sd.n;
   const long long vi = active ? v : sd.n - 1;  // tail lanes shadow the last vertex
 
+  double t0 = sd.t0, dt = sd.dt;
+  const void* src = sd.state;
+  void* dst = sd.state;
+  if constexpr (Pred == kPredRos2) {
+    if (args.ctl) {  // adaptive attempt: time, step and buffers from the control block
+      const AdaptCtl* c = args.ctl;
+      if (c->done) return;
+      t0 = c->t;
+      dt = c->tau;
+      if (c->cur)
+        src = args.state_alt;
+      else
+        dst = args.state_alt;
+    }
+  }
+
   const auto& p = args.params;
   const TE stim_amp = sd.i_stim ? TE(sd.i_stim[vi]) : TE(0);
   const TE diff = sd.i_diff ? TE(sd.i_diff[vi]) : TE(0);
-  const double dt = sd.dt;
   TE dtau[M - 1];
   double Sdt[M - 1][M];
   static_for<M - 1>([&](auto m) {
@@ -232,54 +304,93 @@ __global__ void __launch_bounds__(kBlock)
   const TE tol = TE(args.tol);
 
   Node X[M];
-  L::load(X[0], sd.state, sd.stride, vi);
+  L::load(X[0], src, sd.stride, vi);
 
   unsigned long long it_total = 0;
   unsigned int it_max = 0, nonconv = 0;
+  TE err_est = TE(0);  // ROS2: largest scaled embedded error of the launch
 
   for (int step = 0; step < sd.n_steps; ++step) {
-    const double t_mid = sd.t0 + (double(sd.step_offset + step) + 0.5) * dt;
+    const double t_mid = t0 + (double(sd.step_offset + step) + 0.5) * dt;
     const TE stim = (sd.t_on <= t_mid && t_mid < sd.t_off) ? stim_amp : TE(0);
+    TE F0[N];  // F(X_n), needed by the sweeps
 
-    // ---- predictor: backward Euler by local Newton on each sub-interval
-    static_for<M - 1>([&](auto MM) {
-      constexpr int m = MM;
-      Node Y = X[m];
-      int it = 0;
-      bool conv = false;
-      do {
-        TE xe[N], f[N], delta[N];
-        L::to_eval(Y, xe);
-        // b = -(Y - X_m - dtau F(Y)), formed in double
-        auto bfn = [&](auto I, TE fi) -> TE {
-          constexpr int i = I;
-          return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
-                    double(dtau[m]) * double(fi));
-        };
-        eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
-        TE err = TE(0);
+    if constexpr (Pred == kPredRos2) {
+      // ---- predictor: one ROS2 step on each sub-interval
+      static_for<M - 1>([&](auto MM) {
+        constexpr int m = MM;
+        TE xe[N], u1[N], u2[N], x2[N], r2[N];
+        L::to_eval(X[m], xe);
+        const TE gt = TE(kRosGamma) * dtau[m];
+        auto b1 = [&](auto, TE fi) -> TE { return gt * fi; };
+        SinkElim<Model, TE, decltype(b1), true> s(gt, b1);
+        call_rhs_FJ<Model, TE>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
+        s.solve(u1);
+        if constexpr (m == 0) static_for<N>([&](auto I) { F0[I] = s.f[I]; });
+        static_for<N>([&](auto I) { x2[I] = xe[I] + TE(kRosA21) * u1[I]; });
+        eval_F<Model, TE>(p, stim, diff, x2, r2);
+        static_for<N>([&](auto I) { r2[I] = gt * r2[I] - TE(2) * u1[I]; });
+        s.resolve(r2, u2);
+        X[m + 1] = X[m];
         static_for<N>([&](auto I) {
           constexpr int i = I;
-          auto& y = L::template at<i>(Y);
-          y += delta[i];
+          auto& y = L::template at<i>(X[m + 1]);
+          y += TE(kRosM1) * u1[i] + TE(kRosM2) * u2[i];
           const TE ay = fabs(TE(y));
-          const TE s = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
-          const TE e = fabs(delta[i]) / s;
-          err = e > err ? e : err;
+          const TE sc = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
+          const TE e = fabs(TE(kRosM2) * (u1[i] + u2[i])) / sc;
+          err_est = (e > err_est || e != e) ? e : err_est;
         });
-        ++it;
-        conv = err <= tol;
-      } while (!conv && it < args.maxit);
-      X[m + 1] = Y;
-      it_total += (unsigned long long)it;
-      it_max = (unsigned int)it > it_max ? (unsigned int)it : it_max;
-      nonconv += conv ? 0u : 1u;
-    });
+      });
+    } else {
+      // ---- predictor: backward Euler by local Newton on each sub-interval.  The
+      // iteration loop is uniform over the wave (it runs while any lane still
+      // iterates; a lane that has stopped keeps its iterate through selects), so
+      // the kernel has no divergent loop exit: at such exits gfx950 builds of
+      // the double kernels placed spill code ahead of the execution-mask restore.
+      static_for<M - 1>([&](auto MM) {
+        constexpr int m = MM;
+        Node Y = X[m];
+        int it = 0;
+        bool conv = false, run = true;
+        do {
+          TE xe[N], f[N], delta[N];
+          L::to_eval(Y, xe);
+          // b = -(Y - X_m - dtau F(Y)), formed in double
+          auto bfn = [&](auto I, TE fi) -> TE {
+            constexpr int i = I;
+            return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
+                      double(dtau[m]) * double(fi));
+          };
+          eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
+          // every quantity below is computed on all lanes and only chosen per
+          // lane, with no conditional evaluation, so no divergent branch forms
+          TE err = TE(0);
+          static_for<N>([&](auto I) {
+            constexpr int i = I;
+            auto& y = L::template at<i>(Y);
+            const auto yn = y + delta[i];
+            y = pick(run, yn, y);
+            const TE ay = fabs(TE(yn));
+            const TE s = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
+            const TE e = fabs(delta[i]) / s;
+            err = e > err ? e : err;
+          });
+          const bool now_conv = err <= tol;
+          it += int(run);
+          conv = (run & now_conv) | (!run & conv);
+          run = run & !conv & (it < args.maxit);
+        } while (__builtin_amdgcn_ballot_w64(run) != 0);
+        X[m + 1] = Y;
+        it_total += (unsigned long long)it;
+        it_max = (unsigned int)it > it_max ? (unsigned int)it : it_max;
+        nonconv += conv ? 0u : 1u;
+      });
+    }
 
     // ---- corrections
     if (sd.n_sweeps > 0) {
-      TE F0[N];
-      {
+      if constexpr (Pred == kPredNewton) {
         TE xe[N];
         L::to_eval(X[0], xe);
         eval_F<Model, TE>(p, stim, diff, xe, F0);
@@ -334,7 +445,16 @@ __global__ void __launch_bounds__(kBlock)
     constexpr int i = I;
     if (!isfinite(double(L::template at<i>(X[0])))) nonfinite = 1;
   });
-  if (active) L::store(X[0], sd.state, sd.stride, v);
+  if (active) L::store(X[0], dst, sd.stride, v);
+
+  if constexpr (Pred == kPredRos2) {
+    if (args.ctl) {  // largest lane error of the attempt; a non-finite state rejects it
+      double e = double(err_est);
+      if (nonfinite || !(e <= 1.0e308)) e = __builtin_inf();
+      const unsigned long long bits = wave_max_u64(active ? (unsigned long long)__double_as_longlong(e) : 0ull);
+      if (threadIdx.x == 0) atomicMax(&args.err[blockIdx.x % kSlots].bits, bits);
+    }
+  }
 
   // wave-level reduction of the statistics, one set of atomics per wave
   const unsigned long long a_iters = wave_sum(active ? it_total : 0ull);
@@ -343,12 +463,14 @@ __global__ void __launch_bounds__(kBlock)
   const unsigned long long a_act = wave_sum(active ? 1ull : 0ull);
   const unsigned int a_itmax = wave_max(active ? it_max : 0u);
   if (threadIdx.x == 0 && sd.stats) {
-    atomicAdd(&sd.stats->vertex_steps, a_act * (unsigned long long)sd.n_steps);
-    atomicAdd(&sd.stats->newton_iters, a_iters);
-    atomicAdd(&sd.stats->newton_solves, a_act * (unsigned long long)sd.n_steps * (M - 1));
-    atomicAdd(&sd.stats->nonconverged, a_nonconv);
-    atomicAdd(&sd.stats->nonfinite, a_nonfin);
-    atomicMax(&sd.stats->it_max, a_itmax);
+    DevStats* st = sd.stats + blockIdx.x % kSlots;
+    atomicAdd(&st->vertex_steps, a_act * (unsigned long long)sd.n_steps);
+    atomicAdd(&st->newton_iters, a_iters);
+    if (Pred == kPredNewton)
+      atomicAdd(&st->newton_solves, a_act * (unsigned long long)sd.n_steps * (M - 1));
+    atomicAdd(&st->nonconverged, a_nonconv);
+    atomicAdd(&st->nonfinite, a_nonfin);
+    atomicMax(&st->it_max, a_itmax);
   }
 }
 

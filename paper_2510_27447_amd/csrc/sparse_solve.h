@@ -66,7 +66,7 @@ struct Elim {
 
 // Receives the rows of F and J (value and partials) in emission order and
 // solves (I - dtau J) delta = b with b_i = bfn(i, F_i).
-template <class Model, class T, class BFn>
+template <class Model, class T, class BFn, bool Keep = false>
 struct SinkElim {
   using E = Elim<Model>;
   static constexpr int N = Model::N;
@@ -77,8 +77,11 @@ struct SinkElim {
   T f[N];          // F at the evaluation point
   T gd[N];         // G rows: b_g / pivot
   T gc[N][NC];     // G rows: a_gk / pivot for core columns k
-  T a[NC][NC];     // core block (on the fill pattern)
+  T a[NC][NC];     // core block (on the fill pattern); multipliers below the diagonal
   T b[NC];
+  T ginv[N];       // Keep: G rows' 1 / pivot
+  T ag[NC][N];     // Keep: core rows' G-column entries -dtau J_ig
+  T pinv[NC];      // Keep: core 1 / pivot
 
   IONIC_DEV SinkElim(T dt, BFn fn) : dtau(dt), bfn(fn) {}
 
@@ -97,6 +100,7 @@ struct SinkElim {
     const T bi = bfn(std::integral_constant<int, i>{}, x.v);
     if constexpr (i >= NC) {
       const T inv = f_rcp(T(1) - dtau * jac<i>(x));
+      if constexpr (Keep) ginv[i] = inv;
       gd[i] = bi * inv;
       for_bits<Model::ROW[i] & ~bit(i)>([&](auto K) {
         constexpr int k = K;
@@ -117,6 +121,7 @@ struct SinkElim {
       for_bits<Model::ROW[i] & E::G_MASK>([&](auto G) {
         constexpr int g = G;
         const T aig = -dtau * jac<g>(x);
+        if constexpr (Keep) ag[i][g] = aig;
         bb -= aig * gd[g];
         for_bits<Model::ROW[g] & ~bit(g)>([&](auto K) {
           constexpr int k = K;
@@ -137,6 +142,7 @@ struct SinkElim {
         constexpr int i = I;
         if constexpr (i > p && E::FILL.p[i][p]) {
           const T l = a[i][p] * inv[p];
+          if constexpr (Keep) a[i][p] = l;
           static_for<NC>([&](auto J) {
             constexpr int jx = J;
             if constexpr (jx > p && E::FILL.p[p][jx]) a[i][jx] -= l * a[p][jx];
@@ -153,6 +159,51 @@ struct SinkElim {
         if constexpr (jx > p && E::FILL.p[p][jx]) acc -= a[p][jx] * delta[jx];
       });
       delta[p] = acc * inv[p];
+    });
+    static_for<N - NC>([&](auto GG) {
+      constexpr int g = NC + GG;
+      T acc = gd[g];
+      for_bits<Model::ROW[g] & ~bit(g)>([&](auto K) {
+        constexpr int k = K;
+        acc -= gc[g][k] * delta[k];
+      });
+      delta[g] = acc;
+    });
+    if constexpr (Keep) static_for<NC>([&](auto P) { pinv[P] = inv[P]; });
+  }
+
+  // After solve(): the solution of the same system for another right-hand side.
+  IONIC_DEV void resolve(const T (&rhs)[N], T (&delta)[N]) {
+    static_assert(Keep, "resolve needs the factorisation kept");
+    static_for<N - NC>([&](auto GG) {
+      constexpr int g = NC + GG;
+      gd[g] = rhs[g] * ginv[g];
+    });
+    T c[NC];
+    static_for<NC>([&](auto I) {
+      constexpr int i = I;
+      T bb = rhs[i];
+      for_bits<Model::ROW[i] & E::G_MASK>([&](auto G) {
+        constexpr int g = G;
+        bb -= ag[i][g] * gd[g];
+      });
+      c[i] = bb;
+    });
+    static_for<NC>([&](auto P) {
+      constexpr int p = P;
+      static_for<NC>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > p && E::FILL.p[i][p]) c[i] -= a[i][p] * c[p];
+      });
+    });
+    static_for<NC>([&](auto PR) {
+      constexpr int p = NC - 1 - PR;
+      T acc = c[p];
+      static_for<NC>([&](auto J) {
+        constexpr int jx = J;
+        if constexpr (jx > p && E::FILL.p[p][jx]) acc -= a[p][jx] * delta[jx];
+      });
+      delta[p] = acc * pinv[p];
     });
     static_for<N - NC>([&](auto GG) {
       constexpr int g = NC + GG;

@@ -17,6 +17,8 @@ import numpy as np
 
 LR91, TT06_EPI, TEST_LINEAR, TEST_LOGISTIC = 1, 2, 90, 91
 FP64, MIXED = 0, 1
+PRED_NEWTON, PRED_ROS2 = 0, 1
+PREDICTORS = {"newton": PRED_NEWTON, "ros2": PRED_ROS2}
 MODEL_IDS = {"LR91": LR91, "TT06": TT06_EPI, "TEST_LINEAR": TEST_LINEAR, "TEST_LOGISTIC": TEST_LOGISTIC}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 
@@ -53,6 +55,18 @@ class ionic_stats(ctypes.Structure):
     ]
 
 
+class ionic_adapt_result(ctypes.Structure):
+    _fields_ = [
+        ("t", c_double),
+        ("dt_next", c_double),
+        ("err_last", c_double),
+        ("accepted", c_int64),
+        ("rejected", c_int64),
+        ("reached", c_int32),
+        ("failed", c_int32),
+    ]
+
+
 _SIGNATURES = {
     "ionic_n_states": (c_int, [c_int]),
     "ionic_n_fp64_states": (c_int, [c_int]),
@@ -67,6 +81,11 @@ _SIGNATURES = {
     "ionic_destroy": (None, [c_void_p]),
     "reaction_sdc_step": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_int, c_void_p,
                                   c_double, c_double, c_void_p, c_void_p]),
+    "ionic_set_predictor": (c_int, [c_void_p, c_int]),
+    "reaction_sdc_adaptive": (c_int, [c_void_p, c_double, c_double, c_double, c_double, c_double,
+                                      c_int, c_int, c_void_p, c_double, c_double, c_void_p,
+                                      c_void_p, c_size_t, c_int64, c_void_p,
+                                      POINTER(ionic_adapt_result), c_void_p]),
     "ionic_set_inputs": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_void_p, c_double,
                                  c_double, c_void_p]),
     "reaction_sdc_step_batch": (c_int, [POINTER(c_void_p), POINTER(c_int), c_int, c_void_p]),
@@ -211,6 +230,22 @@ def reaction_sdc_step(handle, t0, dt, n_steps, n_nodes, n_sweeps, i_stim=None, s
                                    stim_t_on, stim_t_off, _ptr(i_diff), _stream(stream)))
 
 
+def ionic_set_predictor(handle, predictor):
+    _check(lib().ionic_set_predictor(handle, PREDICTORS.get(predictor, predictor)))
+
+
+def reaction_sdc_adaptive(handle, t0, t_end, dt_init, dt_max, err_tol, n_nodes, n_sweeps,
+                          work, work_bytes, max_attempts, i_stim=None, stim_t_on=0.0,
+                          stim_t_off=0.0, i_diff=None, history=None, stream=None):
+    """Returns the ionic_adapt_result fields as a dict (synchronises the stream)."""
+    out = ionic_adapt_result()
+    _check(lib().reaction_sdc_adaptive(handle, t0, t_end, dt_init, dt_max, err_tol, n_nodes,
+                                       n_sweeps, _ptr(i_stim), stim_t_on, stim_t_off, _ptr(i_diff),
+                                       _ptr(work), work_bytes, int(max_attempts), _ptr(history),
+                                       ctypes.byref(out), _stream(stream)))
+    return {name: getattr(out, name) for name, _ in ionic_adapt_result._fields_}
+
+
 def ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0,
                      stim_t_off=0.0, i_diff=None):
     _check(lib().ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, _ptr(i_stim), stim_t_on,
@@ -279,6 +314,29 @@ class Simulation:
              i_diff=None, stream=None):
         reaction_sdc_step(self.handle, t0, dt, n_steps, n_nodes, n_sweeps, i_stim, stim_t_on,
                           stim_t_off, i_diff, stream)
+
+    def set_predictor(self, predictor):
+        ionic_set_predictor(self.handle, predictor)
+
+    def adaptive(self, t0, t_end, dt_init, dt_max, err_tol, n_nodes=2, n_sweeps=1, i_stim=None,
+                 stim_t_on=0.0, stim_t_off=0.0, i_diff=None, max_attempts=100000,
+                 history=False, stream=None):
+        """Adaptive run from t0 to t_end (ROS2 predictor).  Returns the result
+        dict; with history=True also the (attempts, 4) array of (t, tau, err,
+        accepted) rows."""
+        import torch
+        nbytes = ionic_state_bytes(self.model, self.precision, self.n)
+        if getattr(self, "_work", None) is None or self._work.numel() < nbytes:
+            self._work = torch.empty(nbytes, dtype=torch.uint8, device=self.state.device)
+        hist = (torch.zeros((int(max_attempts), 4), dtype=torch.float64, device=self.state.device)
+                if history else None)
+        res = reaction_sdc_adaptive(self.handle, t0, t_end, dt_init, dt_max, err_tol, n_nodes,
+                                    n_sweeps, self._work, nbytes, max_attempts, i_stim, stim_t_on,
+                                    stim_t_off, i_diff, hist, stream)
+        if history:
+            n = res["accepted"] + res["rejected"]
+            return res, hist[:n].cpu().numpy()
+        return res
 
     def readback(self, first=0, count=None, stream=None):
         count = self.n - first if count is None else count

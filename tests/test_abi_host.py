@@ -119,4 +119,20 @@ def test_step_entry_points_reject_bad_arguments():
     assert lib.reaction_sdc_step_batch(None, None, 0, None) == 0
     assert lib.reaction_sdc_step_batch(None, None, 1, None) == -1
     assert lib.reaction_sdc_step_batch(None, None, -1, None) == -1
+    assert lib.ionic_set_predictor(None, 1) == -1
     lib.ionic_destroy(None)
+
+
+def test_adaptive_entry_point_rejects_bad_arguments():
+    lib = I.lib()
+    out = I.ionic_adapt_result()
+    args = [None, 0.0, 1.0, 0.01, 0.05, 1e-3, 2, 1, None, 0.0, 0.0, None, None, 0, 10, None,
+            I.ctypes.byref(out), None]
+    assert lib.reaction_sdc_adaptive(*args) == -1
+    assert "sim" in lib.ionic_last_error().decode()
+
+
+def test_predictor_enum_matches_header():
+    text = open(HEADER).read()
+    for name, val in [("IONIC_PRED_NEWTON", I.PRED_NEWTON), ("IONIC_PRED_ROS2", I.PRED_ROS2)]:
+        assert re.search(r"\b%s\s*=\s*%d\b" % (name, val), text), name

@@ -23,7 +23,8 @@ def test_bench_constants_match_the_counter():
     for model, x, n64, const in ((TT06, tt06.published_initial(), 6, b.TT06_FLOPS),
                                  (LR91, rest.lr91_rest(), 2, b.LR91_FLOPS)):
         ev = per_evaluation(model, x, n64)
-        assert {k: ev[k] for k in ("F", "FJ", "solve")} == const, model.name
+        assert {k: ev[k] for k in ("F", "FJ", "solve", "resolve")} == const, model.name
+        assert ev["resolve"] < ev["solve"]
         assert ev["FJ"] > ev["F"]
     assert per_evaluation(TT06, tt06.published_initial(), 6)["nnz"] == 76
 
@@ -36,3 +37,20 @@ def test_solve_count_on_a_tiny_pattern():
     # l + 1 update(2)+b(2), Cai pivot rcp; back substitution: 3 rows
     assert nnz == 7
     assert flops == (1 + 1 + 2 + 2) + (1 + 1 + 2 + 2) + 1 + (2 * 1 + 1) + (2 * 0 + 1) + (2 * 1 + 1)
+
+
+def test_resolve_count_on_a_tiny_pattern():
+    from oracle.opcount import resolve_flops
+    # same pattern as above: forward b updates (gate into V: 2; V into Cai: 2), back
+    # substitution 3 rows (2 * upper entries + 1)
+    pattern = [[0, 1, 2], [0, 1], [0, 2]]
+    assert resolve_flops(pattern, 2) == 2 + 2 + (2 * 1 + 1) + (2 * 0 + 1) + (2 * 1 + 1)
+
+
+def test_bench_launch_formulas_match_the_counter():
+    from oracle.opcount import flops_per_launch, flops_per_launch_ros2
+    b = _bench()
+    ev = b.TT06_FLOPS
+    for M, K in ((2, 1), (3, 3), (4, 2)):
+        assert b.flops_per_launch_ros2(ev, 19, 1000, M, K) == flops_per_launch_ros2(ev, 19, 1000, M, K)
+        assert b.flops_per_launch(ev, 19, 1000, M, K, 2500) == flops_per_launch(ev, 19, 1000, M, K, 2500)
