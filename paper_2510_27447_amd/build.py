@@ -34,10 +34,8 @@ STEP_MIXED = ["kernels_tt06_mixed.hip", "kernels_tt06_mixed_ros2.hip", "kernels_
 # slowest first, so the parallel build ends sooner
 SOURCES = STEP_FP64 + STEP_MIXED + ["kernels_tt06.hip", "kernels_lr91.hip", "kernels_test.hip",
                                     "control.hip", "ionic.cpp"]
-# per-source optimisation level (default -O3); the double-precision step
-# kernels of the cell models are built at -O1, where their code is exact
-# (see the headers of those files)
-OPT = {s: "-O1" for s in STEP_FP64}
+# per-source optimisation level (default -O3)
+OPT = {}
 # the mixed-precision step kernels may reassociate fp arithmetic (NaN/Inf
 # semantics kept, so non-finite states are still detected); results move at
 # the rounding level only, far below the mixed path's tolerance

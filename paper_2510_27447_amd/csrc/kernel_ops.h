@@ -48,8 +48,7 @@ struct ModelOps {
 
 // The step kernels of the cell models live in translation units of their own
 // (one per model, precision policy and predictor) so they compile in
-// parallel; the double-precision ones are compiled at a lower optimisation
-// level (see the build script and kernels_*_fp64.hip).
+// parallel.
 hipError_t tt06_sdc_fp64_newton(int, const void*, const LaunchCommon&, int, hipStream_t);
 hipError_t tt06_sdc_fp64_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
 hipError_t tt06_sdc_mixed_newton(int, const void*, const LaunchCommon&, int, hipStream_t);

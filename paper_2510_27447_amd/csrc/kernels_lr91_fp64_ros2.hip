@@ -1,7 +1,6 @@
-// Double-precision LR91 step kernels (ROS2 predictor), in a translation
-// unit of their own built at -O1, for the same reason as the TT06 ones: an -O3
-// build of the Newton variant returned non-finite states on gfx950 while -O1
-// and host builds are exact.
+// Double-precision LR91 step kernels (ROS2 predictor), in a translation unit
+// of their own so the model kernels compile in parallel; guarded by the
+// build's codegen check like the other double kernels.
 #include "kernel_ops_impl.h"
 #include "model_lr91.h"
 

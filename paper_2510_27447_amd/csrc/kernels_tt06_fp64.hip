@@ -1,8 +1,7 @@
-// Double-precision TT06 step kernels (Newton predictor), in a translation
-// unit of their own: the build compiles it at -O1.  At -O3 the Newton variant
-// of this kernel (over 256 VGPRs plus AGPRs and scratch at one wave per SIMD)
-// returned corrupted state on gfx950 while the same source at -O1, and on the
-// host, matches the reference to 1e-15; the other double kernels follow suit.
+// Double-precision TT06 step kernels (Newton predictor), in a translation unit
+// of their own so the model kernels compile in parallel.  These kernels need
+// all 512 vector registers and still spill; the build's codegen check guards
+// them against spill code placed ahead of an execution-mask restore.
 #include "kernel_ops_impl.h"
 #include "model_tt06.h"
 
