@@ -16,7 +16,9 @@ nodal evaluation of the reaction terms).  One step from t_n to t_n + dt:
    (b) one step of the Rosenbrock method ROS2 (equation rb_system, module
        ros2), the paper's own predictor, which also yields the scaled
        embedded error max_i |X_i - X_hat_i| / max(|X_i|, scale_i) used for
-       step-size control;
+       step-size control; or
+   (c) Rush-Larsen (module rush_larsen): exponential steps for the gating
+       states at frozen X_m, then backward Euler by Newton on the core;
 3. K sweeps of the linearised implicit correction (equations residual,
    sdc_ode, sdc generalised from the trapezoid to M nodes):
    F^k_j = F(X^k_j);  X^{k+1}_0 = X_n;  for m = 0..M-2
@@ -37,6 +39,7 @@ import numpy as np
 
 from .lobatto import integration_matrix, nodes
 from .ros2 import ros2_step
+from .rush_larsen import rush_larsen_be
 
 
 @dataclass
@@ -101,7 +104,7 @@ def embedded_error(model, X, X_hat):
     return np.max(np.abs(X - X_hat) / np.maximum(np.abs(X), scale), axis=0)
 
 
-PREDICTORS = ("newton", "ros2")
+PREDICTORS = ("newton", "ros2", "rush_larsen")
 
 
 def sdc_step(model, Xn, i_stim, dt, M, K, i_diff, tol, maxit, clamp_v, stats, S, c,
@@ -124,6 +127,10 @@ def sdc_step(model, Xn, i_stim, dt, M, K, i_diff, tol, maxit, clamp_v, stats, S,
             Xnew, Xhat, _ = ros2_step(model, Xk[m], dtau[m], i_stim, i_diff, clamp_v)
             err = np.maximum(err, embedded_error(model, Xnew, Xhat))
             Xk.append(Xnew)
+    elif predictor == "rush_larsen":
+        for m in range(M - 1):
+            Xk.append(rush_larsen_be(model, Xk[m], dtau[m], i_stim, i_diff, tol, maxit, clamp_v,
+                                     stats))
     else:
         raise ValueError("unknown predictor %r" % (predictor,))
     # corrections
