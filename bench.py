@@ -37,6 +37,8 @@ import numpy as np
 # `python -m oracle.opcount`, checked against it by the CPU tests).
 TT06_FLOPS = {"F": 553, "FJ": 1250, "solve": 362, "resolve": 155}
 LR91_FLOPS = {"F": 232, "FJ": 465, "solve": 75, "resolve": 40}
+# Rush-Larsen evaluations (work feeding the outputs the kernel keeps)
+TT06_RL_FLOPS = {"gate_step_first": 568, "gate_step": 335, "core_FJ": 572, "core_solve": 174}
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector fp64 / fp32 (published)
 HBM_PEAK_GBS = 8000.0
 
@@ -143,6 +145,18 @@ def flops_per_launch_ros2(ev, n_states, vertex_steps, M, K):
     return vertex_steps * ((M - 1) * per_sub + sweeps)
 
 
+def flops_per_launch_rl(ev, rl, n_states, n_core, vertex_steps, M, K, newton_iters):
+    """Rush-Larsen predictor: gating-state evaluations (the first gives F(X_n)),
+    7 flops per gating state and sub-interval, per core Newton iteration the
+    core evaluation, core solve and 6 flops per core state; sweeps as above."""
+    gates = n_states - n_core
+    per_step = rl["gate_step_first"] + (M - 2) * rl["gate_step"] + (M - 1) * 7 * gates
+    sweeps = (K * (M - 2) * ev["F"] + K * (M - 1) * (ev["FJ"] + ev["solve"])
+              + K * ((M - 1) * M * 2 + (M - 1) * 3) * n_states)
+    return (vertex_steps * (per_step + sweeps)
+            + newton_iters * (rl["core_FJ"] + rl["core_solve"] + 6 * n_core))
+
+
 def state_bytes_per_vertex(precision):
     return 19 * 8 if precision == "fp64" else 6 * 8 + 13 * 4
 
@@ -185,6 +199,9 @@ def run_pass_set(I, torch, w, steps, warmup, predictor="newton"):
     iters = st["newton_iters"] / steps
     if predictor == "newton":
         flops = flops_per_launch(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps, iters)
+    elif predictor == "rush_larsen":
+        flops = flops_per_launch_rl(TT06_FLOPS, TT06_RL_FLOPS, 19, 6, vsteps, w.n_nodes,
+                                    w.n_sweeps, iters)
     else:
         flops = flops_per_launch_ros2(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps)
     kavg = float(np.mean(kernel_ms)) / 1e3
@@ -286,6 +303,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--no-ros2", action="store_true")
+    ap.add_argument("--no-rl", action="store_true")
     ap.add_argument("--adaptive-tol", type=float, default=1e-3)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
@@ -342,6 +360,18 @@ def main():
             a["V_error_vs_fp64_newton"] = verr(a.pop("V"))
             ros2["adaptive"][prec] = a
 
+    rl = None
+    if not args.no_rl:
+        # the headline workload (3 nodes, 3 sweeps) with the Rush-Larsen predictor
+        rl = {}
+        for prec in ("mixed", "fp64"):
+            w = W.c2_tt06(precision=prec)
+            print("[bench] rush-larsen %s" % prec, file=sys.stderr, flush=True)
+            r = run_pass_set(I, torch, w, args.steps, args.warmup, predictor="rush_larsen")
+            r["V_error_vs_fp64_newton"] = verr(r.pop("V"))
+            rl[prec] = {k: r[k] for k in ("value", "kernel_ms", "roofline", "newton_iters_per_solve",
+                                          "V_error_vs_fp64_newton", "n_nonfinite")}
+
     serving = None
     if not args.no_serving:
         from paper_2510_27447_amd import serve
@@ -386,6 +416,7 @@ def main():
         "cpu_baseline": cpu,
         "serving": serving,
         "ros2_sdc": ros2,
+        "rush_larsen": rl,
     }
     print(json.dumps(out))
 

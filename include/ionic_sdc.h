@@ -78,8 +78,15 @@ enum {
  * implicit integrator of the correction equation, section 3.3.2).
  * IONIC_PRED_ROS2: one step of the two-stage, second-order, L-stable
  * Rosenbrock method ROS2 (section 3.3.1, equation rb_system) with
- * gamma = 1 + 1/sqrt(2), exact Jacobian, both stages on one factorisation. */
-enum { IONIC_PRED_NEWTON = 0, IONIC_PRED_ROS2 = 1 };
+ * gamma = 1 + 1/sqrt(2), exact Jacobian, both stages on one factorisation.
+ * IONIC_PRED_RUSH_LARSEN: the gating states (every state after the
+ * ionic_n_fp64_states core: gates, and for TT06 fCass and Rbar) take the
+ * exponential step g + dtau F_g (e^z - 1)/z, z = dtau dF_g/dg, at frozen X_m
+ * (exact for their rows, which are linear in the state itself); then
+ * backward Euler by local Newton on the core alone with the gates held, with
+ * the same stop rule as IONIC_PRED_NEWTON.  Without gating states it equals
+ * IONIC_PRED_NEWTON. */
+enum { IONIC_PRED_NEWTON = 0, IONIC_PRED_ROS2 = 1, IONIC_PRED_RUSH_LARSEN = 2 };
 
 #define IONIC_MAX_NODES 5   /* Gauss-Lobatto nodes per step: 2..5 */
 #define IONIC_MAX_SWEEPS 16 /* SDC corrections per step: 0..16   */
@@ -182,7 +189,8 @@ int reaction_sdc_step(ionic_sim* sim, double t0, double dt, int n_steps, int n_n
 
 /* Choose the predictor used by reaction_sdc_step and reaction_sdc_step_batch
  * on this handle (default IONIC_PRED_NEWTON).  With IONIC_PRED_ROS2 the
- * Newton settings of the config are unused and the Newton counters stay 0.
+ * Newton settings of the config are unused and the Newton counters stay 0;
+ * with IONIC_PRED_RUSH_LARSEN they count the core Newton iterations.
  * Host only; takes effect for work enqueued afterwards. */
 int ionic_set_predictor(ionic_sim* sim, int predictor);
 

@@ -27,10 +27,8 @@ OBJDIR = os.path.join(LIBDIR, "obj")
 LIBNAME = "libionic_sdc.so"
 LIBPATH = os.path.join(LIBDIR, LIBNAME)
 
-STEP_FP64 = ["kernels_tt06_fp64.hip", "kernels_tt06_fp64_ros2.hip", "kernels_lr91_fp64.hip",
-             "kernels_lr91_fp64_ros2.hip"]
-STEP_MIXED = ["kernels_tt06_mixed.hip", "kernels_tt06_mixed_ros2.hip", "kernels_lr91_mixed.hip",
-              "kernels_lr91_mixed_ros2.hip"]
+STEP_FP64 = ["kernels_%s_fp64%s.hip" % (m, p) for m in ("tt06", "lr91") for p in ("", "_ros2", "_rl")]
+STEP_MIXED = ["kernels_%s_mixed%s.hip" % (m, p) for m in ("tt06", "lr91") for p in ("", "_ros2", "_rl")]
 # slowest first, so the parallel build ends sooner
 SOURCES = STEP_FP64 + STEP_MIXED + ["kernels_tt06.hip", "kernels_lr91.hip", "kernels_test.hip",
                                     "control.hip", "ionic.cpp"]

@@ -346,7 +346,8 @@ int reaction_sdc_step(ionic_sim* s, double t0, double dt, int n_steps, int n_nod
 
 int ionic_set_predictor(ionic_sim* s, int predictor) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
-  if (predictor != IONIC_PRED_NEWTON && predictor != IONIC_PRED_ROS2)
+  if (predictor != IONIC_PRED_NEWTON && predictor != IONIC_PRED_ROS2 &&
+      predictor != IONIC_PRED_RUSH_LARSEN)
     return fail(IONIC_EUNSUPPORTED, "unknown predictor " + std::to_string(predictor));
   s->predictor = predictor;
   return IONIC_OK;

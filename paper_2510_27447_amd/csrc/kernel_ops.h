@@ -34,8 +34,8 @@ struct ModelOps {
   const char* const* state_names;
   size_t params_bytes[2];        // sizeof(Params<double>), sizeof(Params<float>)
   void (*derive)(const double* raw, void* p64, void* p32);
-  // fused step kernels, [precision policy: double, mixed][predictor: Newton, ROS2]
-  SdcLaunch sdc[2][2];
+  // fused step kernels, [precision policy: double, mixed][predictor: Newton, ROS2, Rush-Larsen]
+  SdcLaunch sdc[2][3];
   hipError_t (*pack)(int prec, const double* src, long long ld, void* state, long long stride,
                      long long first, long long count, hipStream_t st);
   hipError_t (*unpack)(int prec, const void* state, long long stride, long long first,
@@ -57,6 +57,10 @@ hipError_t lr91_sdc_fp64_newton(int, const void*, const LaunchCommon&, int, hipS
 hipError_t lr91_sdc_fp64_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
 hipError_t lr91_sdc_mixed_newton(int, const void*, const LaunchCommon&, int, hipStream_t);
 hipError_t lr91_sdc_mixed_ros2(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t tt06_sdc_fp64_rl(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t tt06_sdc_mixed_rl(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t lr91_sdc_fp64_rl(int, const void*, const LaunchCommon&, int, hipStream_t);
+hipError_t lr91_sdc_mixed_rl(int, const void*, const LaunchCommon&, int, hipStream_t);
 
 // Adaptive step control (control.hip).
 hipError_t adapt_init(AdaptCtl* c, ErrSlot* err, double t0, double t_end, double dt_init,

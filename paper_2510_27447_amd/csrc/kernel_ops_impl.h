@@ -119,6 +119,8 @@ struct OpsImpl {
       o.sdc[0][kPredRos2] = &sdc<Fp64, kPredRos2>;
       o.sdc[1][kPredNewton] = &sdc<Mixed, kPredNewton>;
       o.sdc[1][kPredRos2] = &sdc<Mixed, kPredRos2>;
+      o.sdc[0][kPredRushLarsen] = &sdc<Fp64, kPredRushLarsen>;
+      o.sdc[1][kPredRushLarsen] = &sdc<Mixed, kPredRushLarsen>;
     }
     o.pack = &pack;
     o.unpack = &unpack;

@@ -1,0 +1,10 @@
+// Mixed-precision TT06 step kernels (Rush-Larsen predictor), in a translation unit
+// of their own so the model kernels compile in parallel.
+#include "kernel_ops_impl.h"
+#include "model_tt06.h"
+
+namespace ionic {
+hipError_t tt06_sdc_mixed_rl(int M, const void* params, const LaunchCommon& c, int blocks, hipStream_t st) {
+  return OpsImpl<TT06>::sdc<Mixed, kPredRushLarsen>(M, params, c, blocks, st);
+}
+}  // namespace ionic

@@ -12,7 +12,12 @@
 //               one F+J evaluation and elimination at X_m, one F evaluation at
 //               X_m + k_1/gamma and a second solve with the kept
 //               factorisation; the embedded solution X_m + k_1/gamma gives the
-//               scaled error estimate used for step-size control;
+//               scaled error estimate used for step-size control; or
+//               (Rush-Larsen) exponential steps g + dtau F_g phi(dtau J_gg)
+//               for the gating states at frozen X_m (one evaluation seeded
+//               on the gating states), then backward Euler on the core by
+//               local Newton with the gates held, each iteration an
+//               evaluation seeded on the core only and a dense core solve;
 //   corrections K times: F at every node, quadrature Q_m = sum_j S_mj dt F_j,
 //               then node by node r = X^{k+1}_m - X^k_{m+1} + Q_m and
 //               (I - dtau_m J(X^k_{m+1})) delta = r, X^{k+1}_{m+1} += delta
@@ -41,6 +46,7 @@ namespace ionic {
 constexpr int kMaxNodes = 5;
 constexpr int kPredNewton = 0;
 constexpr int kPredRos2 = 1;
+constexpr int kPredRushLarsen = 2;
 
 // ROS2 coefficients in the form of equation rb_system multiplied through by
 // tau * gamma:  (I - gamma tau J) k_1 = gamma tau F(X),
@@ -140,6 +146,25 @@ struct SinkF {
   }
 };
 
+// F of every row and the diagonal Jacobian entry of the gating rows (the
+// evaluation is seeded on the gating states only)
+template <class Model, class T>
+struct SinkGateStep {
+  T f[Model::N];
+  T d[Model::N];
+  template <int i, uint32_t M>
+  IONIC_DEV void put(const D<T, M>& x) {
+    static_assert((M & ~Model::ROW[i]) == 0, "F_i depends on a state outside its declared row");
+    f[i] = x.v;
+    if constexpr (i >= Model::N64) {
+      if constexpr (has(M, i))
+        d[i] = x.template d<i>();
+      else
+        d[i] = T(0);
+    }
+  }
+};
+
 // dense F and J (debug entry point)
 template <class Model, class T>
 struct SinkDense {
@@ -220,6 +245,21 @@ template <class Model, class T, class Sink, size_t... I>
 IONIC_DEV void call_rhs_FJ(const typename Model::template Params<T>& p, T stim, T diff, Sink& s,
                            const T (&x)[Model::N], std::index_sequence<I...>) {
   Model::rhs(p, stim, diff, s, seed<T, int(I)>(x[I])...);
+}
+
+// evaluation seeded on the states in Mask only (their partials are carried,
+// every other state enters as a plain value)
+template <class T, int I, uint32_t Mask>
+IONIC_DEV auto seed_if(T x) {
+  if constexpr (has(Mask, I))
+    return seed<T, I>(x);
+  else
+    return plain(x);
+}
+template <class Model, class T, uint32_t Mask, class Sink, size_t... I>
+IONIC_DEV void call_rhs_masked(const typename Model::template Params<T>& p, T stim, T diff, Sink& s,
+                               const T (&x)[Model::N], std::index_sequence<I...>) {
+  Model::rhs(p, stim, diff, s, seed_if<T, int(I), Mask>(x[I])...);
 }
 
 template <class Model, class T>
@@ -341,6 +381,63 @@ __global__ void __launch_bounds__(kBlock)
           const TE e = fabs(TE(kRosM2) * (u1[i] + u2[i])) / sc;
           err_est = (e > err_est || e != e) ? e : err_est;
         });
+      });
+    } else if constexpr (Pred == kPredRushLarsen) {
+      // ---- predictor: Rush-Larsen gating steps, then backward Euler on the core
+      constexpr int NC = Model::N64;
+      constexpr uint32_t CORE = (1u << NC) - 1u;
+      constexpr uint32_t GATES = ((N >= 32) ? 0xFFFFFFFFu : ((1u << N) - 1u)) & ~CORE;
+      static_for<M - 1>([&](auto MM) {
+        constexpr int m = MM;
+        Node Y = X[m];
+        {
+          TE xe[N];
+          L::to_eval(X[m], xe);
+          SinkGateStep<Model, TE> s;
+          call_rhs_masked<Model, TE, GATES>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
+          if constexpr (m == 0) static_for<N>([&](auto I) { F0[I] = s.f[I]; });
+          static_for<N - NC>([&](auto GG) {
+            constexpr int g = NC + GG;
+            const TE z = dtau[m] * s.d[g];
+            const bool z0 = z == TE(0);
+            const TE phi = pick(z0, TE(1), f_expm1(z) * f_rcp(pick(z0, TE(1), z)));
+            L::template at<g>(Y) = TE(L::template at<g>(X[m])) + dtau[m] * s.f[g] * phi;
+          });
+        }
+        int it = 0;
+        bool conv = false, run = true;
+        do {
+          TE xe[N], delta[NC];
+          L::to_eval(Y, xe);
+          // core rows: b = -(Y - X_m - dtau F(Y)), formed in double
+          auto bfn = [&](auto I, TE fi) -> TE {
+            constexpr int i = I;
+            return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
+                      double(dtau[m]) * double(fi));
+          };
+          SinkCore<Model, TE, decltype(bfn)> s(dtau[m], bfn);
+          call_rhs_masked<Model, TE, CORE>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
+          s.solve(delta);
+          TE err = TE(0);
+          static_for<NC>([&](auto I) {
+            constexpr int i = I;
+            auto& y = L::template at<i>(Y);
+            const auto yn = y + delta[i];
+            y = pick(run, yn, y);
+            const TE ay = fabs(TE(yn));
+            const TE sc = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
+            const TE e = fabs(delta[i]) / sc;
+            err = e > err ? e : err;
+          });
+          const bool now_conv = err <= tol;
+          it += int(run);
+          conv = (run & now_conv) | (!run & conv);
+          run = run & !conv & (it < args.maxit);
+        } while (__builtin_amdgcn_ballot_w64(run) != 0);
+        X[m + 1] = Y;
+        it_total += (unsigned long long)it;
+        it_max = (unsigned int)it > it_max ? (unsigned int)it : it_max;
+        nonconv += conv ? 0u : 1u;
       });
     } else {
       // ---- predictor: backward Euler by local Newton on each sub-interval.  The
@@ -466,7 +563,7 @@ __global__ void __launch_bounds__(kBlock)
     DevStats* st = sd.stats + blockIdx.x % kSlots;
     atomicAdd(&st->vertex_steps, a_act * (unsigned long long)sd.n_steps);
     atomicAdd(&st->newton_iters, a_iters);
-    if (Pred == kPredNewton)
+    if (Pred != kPredRos2)
       atomicAdd(&st->newton_solves, a_act * (unsigned long long)sd.n_steps * (M - 1));
     atomicAdd(&st->nonconverged, a_nonconv);
     atomicAdd(&st->nonfinite, a_nonfin);

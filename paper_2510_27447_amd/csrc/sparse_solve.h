@@ -217,4 +217,94 @@ struct SinkElim {
   }
 };
 
+// ---- the core block alone --------------------------------------------------------
+// The Rush-Larsen predictor holds the gating states and solves only for the
+// core (states [0, NC)): (I - dtau J_cc) delta_c = b_c.  Its pattern is the
+// core block of the model's rows with the fill of eliminating it in order.
+template <class Model>
+struct CoreElim {
+  static constexpr int NC = Model::N64;
+  struct Pat {
+    bool p[NC][NC];
+  };
+  static constexpr Pat filled() {
+    Pat P{};
+    for (int i = 0; i < NC; ++i)
+      for (int k = 0; k < NC; ++k) P.p[i][k] = (i == k) || has(Model::ROW[i], k);
+    for (int p = 0; p < NC; ++p)
+      for (int i = p + 1; i < NC; ++i) {
+        if (!P.p[i][p]) continue;
+        for (int j = p + 1; j < NC; ++j)
+          if (P.p[p][j]) P.p[i][j] = true;
+      }
+    return P;
+  }
+  static constexpr Pat FILL = filled();
+};
+
+// Receives the rows of an evaluation seeded on the core states only and keeps
+// the core rows: b_i = bfn(i, F_i) and the core block of I - dtau J.  The rows
+// of the gating states are not used, so their arithmetic is dead code.
+template <class Model, class T, class BFn>
+struct SinkCore {
+  using E = CoreElim<Model>;
+  static constexpr int NC = E::NC;
+
+  T dtau;
+  BFn bfn;
+  T a[NC][NC];
+  T b[NC];
+
+  IONIC_DEV SinkCore(T dt, BFn fn) : dtau(dt), bfn(fn) {}
+
+  template <int i, uint32_t M>
+  IONIC_DEV void put(const D<T, M>& x) {
+    static_assert((M & ~Model::ROW[i]) == 0, "row has an entry outside its declared pattern");
+    if constexpr (i < NC) {
+      b[i] = bfn(std::integral_constant<int, i>{}, x.v);
+      static_for<NC>([&](auto K) {
+        constexpr int k = K;
+        if constexpr (k == i) {
+          if constexpr (has(M, k))
+            a[i][k] = T(1) - dtau * x.template d<k>();
+          else
+            a[i][k] = T(1);
+        } else if constexpr (has(M, k)) {
+          a[i][k] = -dtau * x.template d<k>();
+        } else if constexpr (E::FILL.p[i][k]) {
+          a[i][k] = T(0);
+        }
+      });
+    }
+  }
+
+  IONIC_DEV void solve(T (&delta)[NC]) {
+    T inv[NC];
+    static_for<NC>([&](auto P) {
+      constexpr int p = P;
+      inv[p] = f_rcp(a[p][p]);
+      static_for<NC>([&](auto I) {
+        constexpr int i = I;
+        if constexpr (i > p && E::FILL.p[i][p]) {
+          const T l = a[i][p] * inv[p];
+          static_for<NC>([&](auto J) {
+            constexpr int jx = J;
+            if constexpr (jx > p && E::FILL.p[p][jx]) a[i][jx] -= l * a[p][jx];
+          });
+          b[i] -= l * b[p];
+        }
+      });
+    });
+    static_for<NC>([&](auto PR) {
+      constexpr int p = NC - 1 - PR;
+      T acc = b[p];
+      static_for<NC>([&](auto J) {
+        constexpr int jx = J;
+        if constexpr (jx > p && E::FILL.p[p][jx]) acc -= a[p][jx] * delta[jx];
+      });
+      delta[p] = acc * inv[p];
+    });
+  }
+};
+
 }  // namespace ionic

@@ -17,8 +17,8 @@ import numpy as np
 
 LR91, TT06_EPI, TEST_LINEAR, TEST_LOGISTIC = 1, 2, 90, 91
 FP64, MIXED = 0, 1
-PRED_NEWTON, PRED_ROS2 = 0, 1
-PREDICTORS = {"newton": PRED_NEWTON, "ros2": PRED_ROS2}
+PRED_NEWTON, PRED_ROS2, PRED_RUSH_LARSEN = 0, 1, 2
+PREDICTORS = {"newton": PRED_NEWTON, "ros2": PRED_ROS2, "rush_larsen": PRED_RUSH_LARSEN}
 MODEL_IDS = {"LR91": LR91, "TT06": TT06_EPI, "TEST_LINEAR": TEST_LINEAR, "TEST_LOGISTIC": TEST_LOGISTIC}
 PRECISIONS = {"fp64": FP64, "mixed": MIXED}
 

@@ -134,5 +134,6 @@ def test_adaptive_entry_point_rejects_bad_arguments():
 
 def test_predictor_enum_matches_header():
     text = open(HEADER).read()
-    for name, val in [("IONIC_PRED_NEWTON", I.PRED_NEWTON), ("IONIC_PRED_ROS2", I.PRED_ROS2)]:
+    for name, val in [("IONIC_PRED_NEWTON", I.PRED_NEWTON), ("IONIC_PRED_ROS2", I.PRED_ROS2),
+                      ("IONIC_PRED_RUSH_LARSEN", I.PRED_RUSH_LARSEN)]:
         assert re.search(r"\b%s\s*=\s*%d\b" % (name, val), text), name

@@ -54,3 +54,23 @@ def test_bench_launch_formulas_match_the_counter():
     for M, K in ((2, 1), (3, 3), (4, 2)):
         assert b.flops_per_launch_ros2(ev, 19, 1000, M, K) == flops_per_launch_ros2(ev, 19, 1000, M, K)
         assert b.flops_per_launch(ev, 19, 1000, M, K, 2500) == flops_per_launch(ev, 19, 1000, M, K, 2500)
+
+
+def test_tape_counter_reproduces_the_full_counts():
+    from oracle.opcount import needed_work
+    for model, x, n64 in ((TT06, tt06.published_initial(), 6), (LR91, rest.lr91_rest(), 2)):
+        ev = per_evaluation(model, x, n64)
+        n = model.n
+        assert needed_work(model, x, set(), range(n), []) == ev["F"]
+        assert needed_work(model, x, set(range(n)), range(n), range(n)) == ev["FJ"]
+        # fewer outputs never cost more
+        assert needed_work(model, x, set(range(n64)), range(n64), range(n64)) < ev["FJ"]
+
+
+def test_bench_rush_larsen_constants_and_formula():
+    from oracle.opcount import flops_per_launch_rl, rush_larsen_counts
+    b = _bench()
+    assert rush_larsen_counts(TT06, tt06.published_initial(), 6) == b.TT06_RL_FLOPS
+    for M, K in ((2, 1), (3, 3)):
+        assert (b.flops_per_launch_rl(b.TT06_FLOPS, b.TT06_RL_FLOPS, 19, 6, 1000, M, K, 2400)
+                == flops_per_launch_rl(b.TT06_FLOPS, b.TT06_RL_FLOPS, 19, 6, 1000, M, K, 2400))
