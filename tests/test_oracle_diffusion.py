@@ -1,0 +1,140 @@
+"""Pins of the oracle's diffusion current (paper section 3.1: Q1 finite
+elements on a structured grid, lumped mass; section 4: sigma_i = sigma_e =
+1.5e-3) and of the reaction-diffusion coupling built on it.
+
+* Assembly: A symmetric with zero row sums; the lumped mass tiles the domain;
+  the current conserves the integral of V (Neumann boundaries).
+* Consistency: zero current for linear fields; the exact Laplacian of x^2,
+  y^2, z^2 (and zero for xy) at interior nodes; the classic 3-point stencil in
+  1D and the 9-point stencil (8 at the centre, -1 at the eight neighbours,
+  over 3 h^2) in 2D.
+* The monodomain reading: for sigma_e = lambda sigma_i, a sparse solve of the
+  discrete elliptic equation A_ie u = -A_i v gives -A_i v - A_i u =
+  -(lambda/(1+lambda)) A_i v.
+* Physiology against printed values (tests/golden/paper_biomarkers.json): the
+  planar conduction velocity at the paper's h and conductivities.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import rest, tt06
+from oracle.diffusion import Diffusion, advance_coupled, assemble, monodomain_sigma
+from oracle.models import LR91, TT06
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "paper_biomarkers.json")
+
+
+def coords(shape, h):
+    nx, ny, nz = shape
+    idx = np.arange(nx * ny * nz)
+    return (idx % nx) * h, (idx // nx % ny) * h, (idx // (nx * ny)) * h
+
+
+def interior(shape):
+    nx, ny, nz = shape
+    i, j, k = [c / 1.0 for c in coords(shape, 1.0)]
+    ok = np.ones(nx * ny * nz, dtype=bool)
+    for c, n in ((i, nx), (j, ny), (k, nz)):
+        if n > 1:
+            ok &= (c > 0) & (c < n - 1)
+    return ok
+
+
+@pytest.mark.parametrize("shape", [(9, 1, 1), (7, 6, 1), (5, 4, 6)])
+def test_assembly_invariants(shape):
+    h = 0.3
+    A, M, ml = assemble(shape, h)
+    assert abs(A - A.T).max() < 1e-14
+    assert np.max(np.abs(A @ np.ones(A.shape[0]))) < 1e-13
+    d = sum(n > 1 for n in shape)
+    vol = np.prod([(n - 1) * h for n in shape if n > 1])
+    assert ml.sum() == pytest.approx(vol, rel=1e-13)
+    assert np.all(ml > 0)
+    D = Diffusion(shape, h, 0.7)
+    v = np.random.Generator(np.random.PCG64(1)).normal(size=A.shape[0])
+    assert abs(np.dot(ml, D.current(v))) < 1e-12 * np.abs(v).sum()
+
+
+@pytest.mark.parametrize("shape", [(9, 1, 1), (8, 7, 1), (6, 5, 7)])
+def test_linear_and_quadratic_fields(shape):
+    h, s = 0.25, 1.3
+    D = Diffusion(shape, h, s)
+    x, y, z = coords(shape, h)
+    inner = interior(shape)
+    for lin in (2 * x - y + 0.5, 3 * z + x):
+        assert np.max(np.abs(D.current(lin)[inner])) < 1e-12
+    for c, n in zip((x, y, z), shape):
+        if n > 1:
+            np.testing.assert_allclose(D.current(c * c)[inner], 2.0 * s, rtol=1e-12)
+    if shape[1] > 1:
+        assert np.max(np.abs(D.current(x * y)[inner])) < 1e-12
+
+
+def test_known_stencils():
+    h = 0.1
+    D1 = Diffusion((5, 1, 1), h, 1.0)
+    e = np.zeros(5)
+    e[2] = 1.0
+    np.testing.assert_allclose(-D1.current(e) * h * h, [0, -1, 2, -1, 0], atol=1e-12)
+    D2 = Diffusion((5, 5, 1), h, 1.0)
+    e = np.zeros(25)
+    e[12] = 1.0
+    st = (-D2.current(e) * 3 * h * h).reshape(5, 5)
+    want = np.zeros((5, 5))
+    want[1:4, 1:4] = -1.0
+    want[2, 2] = 8.0
+    np.testing.assert_allclose(st, want, atol=1e-11)
+
+
+@pytest.mark.parametrize("lam", [1.0, 0.4])
+def test_bidomain_reduces_to_monodomain(lam):
+    shape, h, si = (9, 8, 1), 0.05, 1.5e-3
+    se = lam * si
+    A, M, ml = assemble(shape, h)
+    Ai, Aie = si * A, (si + se) * A
+    v = np.random.Generator(np.random.PCG64(2)).normal(size=A.shape[0])
+    # A_ie is singular (constants); fix u at node 0 and solve the rest
+    n = A.shape[0]
+    rhs = -(Ai @ v)
+    Ared = Aie[1:, 1:].tocsc()
+    u = np.zeros(n)
+    u[1:] = spla.spsolve(Ared, rhs[1:])
+    lhs = -(Ai @ v) - (Ai @ u)
+    np.testing.assert_allclose(lhs, -monodomain_sigma(si, se) * (A @ v), rtol=1e-9, atol=1e-15)
+    assert monodomain_sigma(1.5e-3, 1.5e-3) == pytest.approx(0.75e-3)
+
+
+def planar_cv(model, x_rest, T, n=150, h=0.01, dt=0.02):
+    D = Diffusion((n, 1, 1), h, monodomain_sigma(1.5e-3, 1.5e-3))
+    X0 = np.tile(x_rest[:, None], (1, n))
+    stim = np.zeros(n)
+    stim[:5] = -100.0
+    act = np.full(n, np.nan)
+
+    def rec(k, t, X):
+        newly = np.isnan(act) & (X[0] > -20.0)
+        act[newly] = t
+
+    advance_coupled(model, X0, D, dt=dt, n_steps=int(round(T / dt)), n_nodes=2, n_sweeps=1,
+                    i_stim=stim, stim_on=0.0, stim_off=2.0, record=rec)
+    return 50 * h / (act[100] - act[50]) * 1000.0
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("model,window", [("LR91", (0.85, 1.15)), ("TT06", (0.85, 1.25))])
+def test_conduction_velocity_near_printed_value(model, window):
+    """Planar wave in a cable at the paper's h and conductivities (a planar
+    wave in 2D sees exactly the cable's stencil).  The oracle gives LR91
+    25.9 cm/s (printed 27.5) and TT06 52.5 cm/s (printed 44.3); reading sigma
+    instead of the monodomain sigma_i sigma_e/(sigma_i+sigma_e) would scale
+    both by sqrt(2) and leave the windows."""
+    ref = json.load(open(GOLDEN))["cv_cm_per_s"][model]
+    if model == "LR91":
+        cv = planar_cv(LR91, rest.lr91_rest(), 42.0)
+    else:
+        cv = planar_cv(TT06, tt06.published_initial(), 22.0)
+    assert window[0] * ref < cv < window[1] * ref, cv
