@@ -270,6 +270,58 @@ def run_adaptive(I, torch, w, err_tol, t_end, dt_max, dt_init=0.01):
     }
 
 
+def run_reaction_diffusion(I, torch, w, steps, warmup, h=0.01, sigma=0.75e-3):
+    """The slab as tissue: per time step the Q1 diffusion current of the V field
+    (h = 0.01 cm, the monodomain sigma of the paper's sigma_i = sigma_e = 1.5e-3)
+    is held over one reaction step -- 500 diffusion launches and 500 one-step
+    reaction launches per pass; stimulus -100 on the first five x-planes for
+    2 ms.  Also times the diffusion kernel alone."""
+    sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
+                       newton_maxit=w.newton_maxit)
+    # a one-plane stimulus drains into the tissue; five planes start a planar wave
+    stim_np = np.where(np.arange(w.n) % w.grid[0] < 5, -100.0, 0.0)
+    stim = torch.as_tensor(stim_np).cuda()
+    work = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    grid = I.make_grid(*w.grid, h=h, sigma=sigma)
+    init = sim.state.clone()
+    stream = torch.cuda.current_stream()
+
+    def one_pass():
+        sim.state.copy_(init)
+        I.reaction_diffusion_step(sim.handle, grid, 0.0, w.dt, w.n_steps, w.n_nodes, w.n_sweeps,
+                                  work, stim, w.stim_t_on, w.stim_t_off, stream=stream)
+
+    for _ in range(warmup):
+        one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_pass()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    V = sim.readback()[0]
+    # diffusion kernel alone, 200 launches between two events
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(200):
+        I.ionic_diffusion_current(sim.handle, grid, work, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    dk = e0.elapsed_time(e1) / 200 / 1e3
+    sim.close()
+    n_act = int(np.sum(V > 0.0))
+    bytes_diff = w.n * 16                      # V read once, I_diff written once
+    return {
+        "value": w.n * w.n_steps * steps / wall,
+        "ms_per_pass": wall / steps * 1e3,
+        "diffusion_kernel_us": dk * 1e6,
+        "diffusion_roofline": {"bound": "hbm", "achieved": round(bytes_diff / dk / 1e9, 1),
+                               "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                               "frac": round(bytes_diff / dk / 1e9 / HBM_PEAK_GBS, 4)},
+        "vertices_depolarised_at_end": n_act,
+    }
+
+
 def cpu_baseline(n_vertices=2048, n_steps=120):
     """The oracle (fp64 numpy, single thread) on a bounded sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -304,6 +356,7 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=256)
     ap.add_argument("--no-ros2", action="store_true")
     ap.add_argument("--no-rl", action="store_true")
+    ap.add_argument("--no-diffusion", action="store_true")
     ap.add_argument("--adaptive-tol", type=float, default=1e-3)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
@@ -332,6 +385,7 @@ def main():
         print("[bench] %s: %.3e vertex-steps/s, kernel %.1f ms" % (prec, res[prec]["value"],
               res[prec]["kernel_ms"]), file=sys.stderr, flush=True)
     Vf, Vm = res["fp64"].pop("V"), res["mixed"].pop("V")
+    m_value = res["mixed"]["value"]
 
     def verr(V):
         return {"max": float(np.max(np.abs(V - Vf)) / np.max(np.abs(Vf))),
@@ -371,6 +425,13 @@ def main():
             r["V_error_vs_fp64_newton"] = verr(r.pop("V"))
             rl[prec] = {k: r[k] for k in ("value", "kernel_ms", "roofline", "newton_iters_per_solve",
                                           "V_error_vs_fp64_newton", "n_nonfinite")}
+
+    rd = None
+    if not args.no_diffusion:
+        w = W.c2_tt06(precision="mixed")
+        print("[bench] reaction-diffusion mixed", file=sys.stderr, flush=True)
+        rd = run_reaction_diffusion(I, torch, w, args.steps, args.warmup)
+        rd["vs_fused_reaction_only"] = rd["value"] / m_value
 
     serving = None
     if not args.no_serving:
@@ -417,6 +478,7 @@ def main():
         "serving": serving,
         "ros2_sdc": ros2,
         "rush_larsen": rl,
+        "reaction_diffusion": rd,
     }
     print(json.dumps(out))
 

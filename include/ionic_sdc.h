@@ -105,6 +105,21 @@ typedef struct {
                            ionic_param_name(); NULL/0 = defaults */
 } ionic_config;
 
+/* A structured grid of nodes for the diffusion current (paper section 3.1:
+ * Q1 elements on quadrilaterals / hexahedra).  Vertex index i + nx*(j + ny*k),
+ * x fastest; nx*ny*nz must equal the simulation's vertex count, ny and nz
+ * at most 65535; an extent of 1 drops that direction (1D cables, 2D sheets).  h: node spacing in cm,
+ * uniform.  sigma: the conductivity in the voltage equation, cm^2/ms (for the
+ * paper's bidomain with sigma_e = lambda sigma_i this is the monodomain
+ * sigma_i sigma_e/(sigma_i + sigma_e): the elliptic solve then gives
+ * -A_i v - A_i u = -(lambda/(1+lambda)) A_i v exactly; 0.75e-3 for
+ * sigma_i = sigma_e = 1.5e-3). */
+typedef struct {
+  int64_t nx, ny, nz;
+  double h;
+  double sigma;
+} ionic_grid;
+
 /* Outcome of reaction_sdc_adaptive. */
 typedef struct {
   double t;            /* time reached (ms); equals t_end when reached == 1       */
@@ -223,6 +238,26 @@ int reaction_sdc_adaptive(ionic_sim* sim, double t0, double t_end, double dt_ini
                           double stim_t_on, double stim_t_off, const double* i_diff_dev,
                           void* work_dev, size_t work_bytes, int64_t max_attempts,
                           double* history_dev, ionic_adapt_result* out, void* hip_stream);
+
+/* Diffusion current of the current V field (section 3.1, equation
+ * semi-parabolic with lumped mass): i_diff_dev[p] = -sigma (M_L^{-1} A v)_p,
+ * A the unit-conductivity Q1 stiffness matrix, M_L the lumped mass,
+ * homogeneous Neumann boundaries.  i_diff_dev: N doubles on the device.
+ * Asynchronous. */
+int ionic_diffusion_current(ionic_sim* sim, const ionic_grid* grid, double* i_diff_dev,
+                            void* hip_stream);
+
+/* Reaction-diffusion stepping: n_steps times, the diffusion current of the
+ * V field at the start of the step (ionic_diffusion_current into
+ * i_diff_work_dev, N doubles) is held over one reaction step (reaction_sdc_step
+ * with the handle's predictor, t_n = t0 + n dt).  The diffusion term is thus
+ * explicit in time, which is stable only for dt <= h^2 / (2 sigma) (the
+ * largest eigenvalue of M_L^{-1} A on these grids is 4/h^2 in 1, 2 and 3
+ * dimensions); larger steps are rejected with IONIC_EINVAL.  Asynchronous. */
+int reaction_diffusion_step(ionic_sim* sim, const ionic_grid* grid, double t0, double dt,
+                            int n_steps, int n_nodes, int n_sweeps, const double* i_stim_dev,
+                            double stim_t_on, double stim_t_off, double* i_diff_work_dev,
+                            void* hip_stream);
 
 /* Store the step inputs of `sim` for reaction_sdc_step_batch (same meaning as
  * the arguments of reaction_sdc_step).  The batch advances the handle's own

@@ -344,6 +344,61 @@ int reaction_sdc_step(ionic_sim* s, double t0, double dt, int n_steps, int n_nod
   return IONIC_OK;
 }
 
+static int check_grid(const ionic_sim* s, const ionic_grid* g) {
+  if (!g) return fail(IONIC_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(IONIC_EINVAL, "grid extents must be >= 1");
+  if ((__int128)g->nx * g->ny * g->nz != (__int128)s->n)
+    return fail(IONIC_EINVAL, "grid nx*ny*nz must equal the vertex count");
+  if (g->ny > 65535 || g->nz > 65535) return fail(IONIC_EINVAL, "grid ny and nz must be <= 65535");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(IONIC_EINVAL, "grid h must be positive");
+  if (!(g->sigma >= 0.0) || !std::isfinite(g->sigma))
+    return fail(IONIC_EINVAL, "grid sigma must be finite and >= 0");
+  return IONIC_OK;
+}
+
+int ionic_diffusion_current(ionic_sim* s, const ionic_grid* g, double* i_diff_dev,
+                            void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_grid(s, g);
+  if (rc != IONIC_OK) return rc;
+  if (!i_diff_dev) return fail(IONIC_EINVAL, "i_diff_dev is NULL");
+  IONIC_HIP(ionic::diffusion_launch(static_cast<const double*>(s->state), g->nx, g->ny, g->nz,
+                                    g->h, g->sigma, i_diff_dev,
+                                    static_cast<hipStream_t>(hip_stream)));
+  return IONIC_OK;
+}
+
+int reaction_diffusion_step(ionic_sim* s, const ionic_grid* g, double t0, double dt, int n_steps,
+                            int n_nodes, int n_sweeps, const double* i_stim_dev, double stim_t_on,
+                            double stim_t_off, double* i_diff_work_dev, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_grid(s, g);
+  if (rc != IONIC_OK) return rc;
+  rc = check_step_args(t0, dt, n_steps, n_nodes, n_sweeps, stim_t_on, stim_t_off);
+  if (rc != IONIC_OK) return rc;
+  if (!i_diff_work_dev) return fail(IONIC_EINVAL, "i_diff_work_dev is NULL");
+  if (dt * g->sigma * 4.0 / (g->h * g->h) > 2.0)
+    return fail(IONIC_EINVAL, "explicit diffusion unstable: dt must be <= h^2 / (2 sigma) = " +
+                                  std::to_string(g->h * g->h / (2.0 * g->sigma)));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  LaunchCommon c;
+  fill_quadrature(n_nodes, c);
+  c.tol = s->tol;
+  c.maxit = s->maxit;
+  c.n_sims = 1;
+  const int blocks = int((s->n + kBlock - 1) / kBlock);
+  const ionic::SdcLaunch launch = s->ops->sdc[s->precision][s->predictor];
+  for (int k = 0; k < n_steps; ++k) {
+    IONIC_HIP(ionic::diffusion_launch(static_cast<const double*>(s->state), g->nx, g->ny, g->nz,
+                                      g->h, g->sigma, i_diff_work_dev, st));
+    c.sims[0] = desc_of(s, t0, dt, i_stim_dev, stim_t_on, stim_t_off, i_diff_work_dev, k, 1,
+                        n_sweeps, 0);
+    hipError_t e = launch(n_nodes, s->params(), c, blocks, st);
+    if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (reaction-diffusion)");
+  }
+  return IONIC_OK;
+}
+
 int ionic_set_predictor(ionic_sim* s, int predictor) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
   if (predictor != IONIC_PRED_NEWTON && predictor != IONIC_PRED_ROS2 &&

@@ -62,6 +62,10 @@ hipError_t tt06_sdc_mixed_rl(int, const void*, const LaunchCommon&, int, hipStre
 hipError_t lr91_sdc_fp64_rl(int, const void*, const LaunchCommon&, int, hipStream_t);
 hipError_t lr91_sdc_mixed_rl(int, const void*, const LaunchCommon&, int, hipStream_t);
 
+// Diffusion current on a structured grid (diffusion.hip).
+hipError_t diffusion_launch(const double* V, long long nx, long long ny, long long nz, double h,
+                            double sigma, double* out, hipStream_t st);
+
 // Adaptive step control (control.hip).
 hipError_t adapt_init(AdaptCtl* c, ErrSlot* err, double t0, double t_end, double dt_init,
                       double dt_max, double tol, double dt_min, double t_on, double t_off,

@@ -67,6 +67,17 @@ class ionic_adapt_result(ctypes.Structure):
     ]
 
 
+class ionic_grid(ctypes.Structure):
+    _fields_ = [("nx", c_int64), ("ny", c_int64), ("nz", c_int64), ("h", c_double),
+                ("sigma", c_double)]
+
+
+def make_grid(nx, ny=1, nz=1, h=0.01, sigma=0.75e-3):
+    g = ionic_grid()
+    g.nx, g.ny, g.nz, g.h, g.sigma = int(nx), int(ny), int(nz), float(h), float(sigma)
+    return g
+
+
 _SIGNATURES = {
     "ionic_n_states": (c_int, [c_int]),
     "ionic_n_fp64_states": (c_int, [c_int]),
@@ -86,6 +97,10 @@ _SIGNATURES = {
                                       c_int, c_int, c_void_p, c_double, c_double, c_void_p,
                                       c_void_p, c_size_t, c_int64, c_void_p,
                                       POINTER(ionic_adapt_result), c_void_p]),
+    "ionic_diffusion_current": (c_int, [c_void_p, POINTER(ionic_grid), c_void_p, c_void_p]),
+    "reaction_diffusion_step": (c_int, [c_void_p, POINTER(ionic_grid), c_double, c_double, c_int,
+                                        c_int, c_int, c_void_p, c_double, c_double, c_void_p,
+                                        c_void_p]),
     "ionic_set_inputs": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_void_p, c_double,
                                  c_double, c_void_p]),
     "reaction_sdc_step_batch": (c_int, [POINTER(c_void_p), POINTER(c_int), c_int, c_void_p]),
@@ -244,6 +259,18 @@ def reaction_sdc_adaptive(handle, t0, t_end, dt_init, dt_max, err_tol, n_nodes, 
                                        _ptr(work), work_bytes, int(max_attempts), _ptr(history),
                                        ctypes.byref(out), _stream(stream)))
     return {name: getattr(out, name) for name, _ in ionic_adapt_result._fields_}
+
+
+def ionic_diffusion_current(handle, grid, out, stream=None):
+    _check(lib().ionic_diffusion_current(handle, ctypes.byref(grid), _ptr(out), _stream(stream)))
+    return out
+
+
+def reaction_diffusion_step(handle, grid, t0, dt, n_steps, n_nodes, n_sweeps, work, i_stim=None,
+                            stim_t_on=0.0, stim_t_off=0.0, stream=None):
+    _check(lib().reaction_diffusion_step(handle, ctypes.byref(grid), t0, dt, n_steps, n_nodes,
+                                         n_sweeps, _ptr(i_stim), stim_t_on, stim_t_off, _ptr(work),
+                                         _stream(stream)))
 
 
 def ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0,

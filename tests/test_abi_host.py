@@ -137,3 +137,11 @@ def test_predictor_enum_matches_header():
     for name, val in [("IONIC_PRED_NEWTON", I.PRED_NEWTON), ("IONIC_PRED_ROS2", I.PRED_ROS2),
                       ("IONIC_PRED_RUSH_LARSEN", I.PRED_RUSH_LARSEN)]:
         assert re.search(r"\b%s\s*=\s*%d\b" % (name, val), text), name
+
+
+def test_diffusion_entry_points_reject_bad_arguments():
+    lib = I.lib()
+    g = I.make_grid(10, 1, 1, h=0.01, sigma=0.75e-3)
+    assert lib.ionic_diffusion_current(None, I.ctypes.byref(g), None, None) == -1
+    assert lib.reaction_diffusion_step(None, I.ctypes.byref(g), 0.0, 0.02, 1, 3, 2, None, 0.0,
+                                       0.0, None, None) == -1
