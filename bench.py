@@ -61,6 +61,9 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+SHORT_FLAGS = ("--no-serving", "--no-cpu", "--no-ros2", "--no-rl", "--no-diffusion")
+
+
 def traffic_from_counters(fetch_csv, write_csv):
     """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0`.
@@ -75,6 +78,9 @@ def traffic_from_counters(fetch_csv, write_csv):
             v = float(r["Counter_Value"]) * 1024.0
             name = r["Kernel_Name"]
             if "sdc_kernel" in name:
+                # the Newton kernels: predictor 0, the last template argument
+                if not name.split(">")[0].rstrip().endswith("0"):
+                    continue
                 kern["fp64" if "Fp64" in name else "mixed"] = v
             elif "copyBuffer" in name and v > 1e6:
                 copies.append(v)
@@ -95,12 +101,14 @@ def traffic_from_counters(fetch_csv, write_csv):
 
 def write_traffic_file(fetch_csv, write_csv):
     t = traffic_from_counters(fetch_csv, write_csv)
-    lines = ["# HBM traffic of sdc_kernel<TT06, *, 3>, TT06 slab 1e6 vertices x 500 steps, per launch",
+    short = "python3 bench.py --steps 1 --warmup 0 " + " ".join(SHORT_FLAGS)
+    lines = ["# HBM traffic of sdc_kernel<TT06, *, 3, Newton>, TT06 slab 1e6 vertices x 500 steps, "
+             "per launch",
              "# commands (repository root, MI355X):",
-             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/p5/fetch -o fetch -- "
-             "python3 bench.py --no-serving --no-cpu --steps 1 --warmup 0",
-             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/p5/write -o write -- "
-             "python3 bench.py --no-serving --no-cpu --steps 1 --warmup 0",
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/final/fetch -o fetch -- "
+             + short,
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/final/write -o write -- "
+             + short,
              "#   python3 bench.py --traffic-from <fetch csv> <write csv>",
              "# counters scaled by their reading for the state-restore copy (known bytes)",
              "source_hash: %s" % kernel_source_hash()]
@@ -294,11 +302,13 @@ def run_reaction_diffusion(I, torch, w, steps, warmup, h=0.01, sigma=0.75e-3):
     for _ in range(warmup):
         one_pass()
     torch.cuda.synchronize()
+    I.ionic_reset_stats(sim.handle)
     t0 = time.perf_counter()
     for _ in range(steps):
         one_pass()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    st = sim.stats()
     V = sim.readback()[0]
     # diffusion kernel alone, 200 launches between two events
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -311,9 +321,17 @@ def run_reaction_diffusion(I, torch, w, steps, warmup, h=0.01, sigma=0.75e-3):
     sim.close()
     n_act = int(np.sum(V > 0.0))
     bytes_diff = w.n * 16                      # V read once, I_diff written once
+    vsteps = w.n * w.n_steps
+    iters = st["newton_iters"] / steps
+    flops = (flops_per_launch(TT06_FLOPS, 19, vsteps, w.n_nodes, w.n_sweeps, iters)
+             + vsteps * 27 * 2)                # the stencil: 27 products and sums per node
+    per_pass = wall / steps
     return {
-        "value": w.n * w.n_steps * steps / wall,
-        "ms_per_pass": wall / steps * 1e3,
+        "value": vsteps * steps / wall,
+        "ms_per_pass": per_pass * 1e3,
+        "newton_iters_per_solve": st["newton_iters"] / max(1, st["newton_solves"]),
+        "alu_tflops_wall": round(flops / per_pass / 1e12, 3),
+        "frac_of_peak_wall": round(flops / per_pass / 1e12 / PEAK_TFLOPS[w.precision], 4),
         "diffusion_kernel_us": dk * 1e6,
         "diffusion_roofline": {"bound": "hbm", "achieved": round(bytes_diff / dk / 1e9, 1),
                                "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -385,7 +403,6 @@ def main():
         print("[bench] %s: %.3e vertex-steps/s, kernel %.1f ms" % (prec, res[prec]["value"],
               res[prec]["kernel_ms"]), file=sys.stderr, flush=True)
     Vf, Vm = res["fp64"].pop("V"), res["mixed"].pop("V")
-    m_value = res["mixed"]["value"]
 
     def verr(V):
         return {"max": float(np.max(np.abs(V - Vf)) / np.max(np.abs(Vf))),
@@ -431,7 +448,6 @@ def main():
         w = W.c2_tt06(precision="mixed")
         print("[bench] reaction-diffusion mixed", file=sys.stderr, flush=True)
         rd = run_reaction_diffusion(I, torch, w, args.steps, args.warmup)
-        rd["vs_fused_reaction_only"] = rd["value"] / m_value
 
     serving = None
     if not args.no_serving:
