@@ -137,7 +137,7 @@ def read_traffic(prec):
 
 
 def flops_per_launch(ev, n_states, vertex_steps, M, K, newton_iters):
-    F_evals = vertex_steps * (1 + K * (M - 2)) if K > 0 else 0
+    F_evals = vertex_steps * K * (M - 2)   # F(X_n) comes from the first Newton evaluation
     FJ = newton_iters + vertex_steps * K * (M - 1)
     return (F_evals * ev["F"] + FJ * (ev["FJ"] + ev["solve"]) + newton_iters * 6 * n_states
             + vertex_steps * K * ((M - 1) * M * 2 + (M - 1) * 3) * n_states)

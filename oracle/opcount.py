@@ -408,7 +408,7 @@ def flops_per_launch(ev, n, n_steps, M, K, newton_iters):
     iterations the launch actually took (the library's statistics)."""
     """n: states per vertex; n_steps: vertex-steps of the launch; newton_iters: total
     Newton iterations of the launch."""
-    F_evals = n_steps * (1 + K * (M - 2)) if K > 0 else 0
+    F_evals = n_steps * K * (M - 2)   # F(X_n) comes from the first Newton evaluation
     FJ = newton_iters + n_steps * K * (M - 1)   # each Newton iteration and each sweep node
     return (F_evals * ev["F"] + FJ * (ev["FJ"] + ev["solve"])
             # Newton residual (3 flops), update and stop test (3 flops) per state

@@ -353,7 +353,7 @@ __global__ void __launch_bounds__(kBlock)
   for (int step = 0; step < sd.n_steps; ++step) {
     const double t_mid = t0 + (double(sd.step_offset + step) + 0.5) * dt;
     const TE stim = (sd.t_on <= t_mid && t_mid < sd.t_off) ? stim_amp : TE(0);
-    TE F0[N];  // F(X_n), needed by the sweeps
+    TE F0[N];  // F(X_n), needed by the sweeps; every predictor evaluates F there first
 
     if constexpr (Pred == kPredRos2) {
       // ---- predictor: one ROS2 step on each sub-interval
@@ -448,7 +448,7 @@ __global__ void __launch_bounds__(kBlock)
       static_for<M - 1>([&](auto MM) {
         constexpr int m = MM;
         Node Y = X[m];
-        int it = 0;
+        int it = 0, pass = 0;
         bool conv = false, run = true;
         do {
           TE xe[N], f[N], delta[N];
@@ -460,6 +460,11 @@ __global__ void __launch_bounds__(kBlock)
                       double(dtau[m]) * double(fi));
           };
           eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
+          // the first iteration on the first sub-interval evaluates at Y = X_n:
+          // its F is the F(X_n) the sweeps need
+          if constexpr (m == 0)
+            static_for<N>([&](auto I) { F0[I] = pick(pass == 0, f[I], F0[I]); });
+          ++pass;
           // every quantity below is computed on all lanes and only chosen per
           // lane, with no conditional evaluation, so no divergent branch forms
           TE err = TE(0);
@@ -487,11 +492,6 @@ __global__ void __launch_bounds__(kBlock)
 
     // ---- corrections
     if (sd.n_sweeps > 0) {
-      if constexpr (Pred == kPredNewton) {
-        TE xe[N];
-        L::to_eval(X[0], xe);
-        eval_F<Model, TE>(p, stim, diff, xe, F0);
-      }
       for (int k = 0; k < sd.n_sweeps; ++k) {
         double Q[M - 1][N];
         static_for<M - 1>([&](auto m) {
