@@ -30,6 +30,7 @@ import itertools
 
 import numpy as np
 import scipy.sparse as sp
+import scipy.sparse.linalg as spla
 
 GAUSS2 = (0.5 - 0.5 / np.sqrt(3.0), 0.5 + 0.5 / np.sqrt(3.0))
 
@@ -43,9 +44,11 @@ def grid_dims(shape):
     return [k for k, n in enumerate(shape) if n > 1]
 
 
-def element_matrices(d, h):
-    """Stiffness K and mass Mm of the Q1 element [0, h]^d, local nodes in
+def element_matrices(d, h, sig=None):
+    """Stiffness K (conductivity diag(sig) over the element's d directions, unit
+    if None) and mass Mm of the Q1 element [0, h]^d, local nodes in
     lexicographic order of their corner bits (bit k = upper end along axis k)."""
+    sig = np.ones(d) if sig is None else np.asarray(sig, dtype=np.float64)
     corners = list(itertools.product((0, 1), repeat=d))
     nloc = len(corners)
     K = np.zeros((nloc, nloc))
@@ -62,21 +65,23 @@ def element_matrices(d, h):
             for k in range(d):
                 grad[a, k] = df[k] * np.prod([f[j] for j in range(d) if j != k]) / h
         wq = w ** d
-        K += wq * grad @ grad.T
+        K += wq * (grad * sig[None, :]) @ grad.T
         Mm += wq * np.outer(phi, phi)
     return corners, K, Mm
 
 
-def assemble(shape, h):
-    """Unit-conductivity stiffness A and consistent mass M (scipy CSR) and the
-    lumped mass (row sums of M) for the node grid `shape` = (nx, ny, nz)."""
+def assemble(shape, h, sigma=None):
+    """Stiffness A (unit conductivity, or the diagonal tensor sigma = (sx, sy,
+    sz)) and consistent mass M (scipy CSR) and the lumped mass (row sums of M)
+    for the node grid `shape` = (nx, ny, nz)."""
     shape = tuple(int(n) for n in shape)
     dims = grid_dims(shape)
     d = len(dims)
     N = int(np.prod(shape))
     if d == 0:
         return sp.csr_matrix((N, N)), sp.identity(N, format="csr"), np.ones(N)
-    corners, K, Mm = element_matrices(d, h)
+    sig = None if sigma is None else np.asarray(sigma, dtype=np.float64)[dims]
+    corners, K, Mm = element_matrices(d, h, sig)
     strides = (1, shape[0], shape[0] * shape[1])
     rows, cols, kv, mv = [], [], [], []
     ranges = [range(shape[k] - 1) for k in dims]
@@ -103,6 +108,59 @@ class Diffusion:
 
     def current(self, v):
         return -self.sigma_m * (self.A @ v) / self.ml
+
+
+class Bidomain:
+    """The partitioned step's spatial part for diagonal conductivity tensors
+    sigma_i, sigma_e (paper section 3.1: A_i with sigma_i, A_ie with
+    sigma_i + sigma_e; section 3.3.2, Algorithm 2: the elliptic equation
+    A_ie u = -A_i v is solved with v fixed, then the parabolic-ODE system with u
+    fixed).  Neumann boundaries leave u defined up to a constant; the lumped-mass
+    mean of u is fixed to zero (a bordered system, solved directly).  The
+    current entering dV/dt is -M_L^{-1} A_i (v + u)."""
+
+    def __init__(self, shape, h, sigma_i, sigma_e):
+        self.shape, self.h = tuple(shape), float(h)
+        self.sigma_i = np.asarray(sigma_i, dtype=np.float64)
+        self.sigma_e = np.asarray(sigma_e, dtype=np.float64)
+        self.Ai, _, self.ml = assemble(shape, h, self.sigma_i)
+        self.Aie, _, _ = assemble(shape, h, self.sigma_i + self.sigma_e)
+        ml = sp.csr_matrix(self.ml[None, :])
+        self.bordered = sp.bmat([[self.Aie, ml.T], [ml, None]], format="csc")
+        self.lu = spla.splu(self.bordered)
+
+    def elliptic(self, v):
+        rhs = np.concatenate([-(self.Ai @ v), [0.0]])
+        return self.lu.solve(rhs)[:-1]
+
+    def current(self, v, u):
+        return -(self.Ai @ (v + u)) / self.ml
+
+
+def advance_bidomain(model, X0, bidomain, *, t0=0.0, dt, n_steps, n_nodes, n_sweeps,
+                     i_stim=None, stim_on=0.0, stim_off=0.0, tol=1e-10, maxit=10,
+                     predictor="newton"):
+    """One pass of the partitioned step per time step: u from the elliptic
+    equation with v^n fixed, the current -M_L^{-1} A_i (v^n + u) held over one
+    reaction step.  Returns (X, u of the last step, Stats)."""
+    from .lobatto import integration_matrix, nodes
+    from .sdc import Stats, sdc_step, stimulus_on
+
+    X = np.array(X0, dtype=np.float64, copy=True)
+    n, N = X.shape
+    stim_amp = np.zeros(N) if i_stim is None else np.asarray(i_stim, dtype=np.float64)
+    c = nodes(n_nodes)
+    S = integration_matrix(n_nodes)
+    stats = Stats(per_vertex_iters=np.zeros(N, dtype=np.int64))
+    u = np.zeros(N)
+    for step in range(n_steps):
+        u = bidomain.elliptic(X[0])
+        i_diff = bidomain.current(X[0], u)
+        stim = stim_amp if stimulus_on(t0, dt, step, stim_on, stim_off) else np.zeros(N)
+        X, _ = sdc_step(model, X, stim, dt, n_nodes, n_sweeps, i_diff, tol, maxit, False, stats,
+                        S, c, predictor)
+    stats.n_nonfinite = int((~np.isfinite(X).all(axis=0)).sum())
+    return X, u, stats
 
 
 def advance_coupled(model, X0, diffusion, *, t0=0.0, dt, n_steps, n_nodes, n_sweeps,

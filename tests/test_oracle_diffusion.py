@@ -11,6 +11,11 @@ elements on a structured grid, lumped mass; section 4: sigma_i = sigma_e =
 * The monodomain reading: for sigma_e = lambda sigma_i, a sparse solve of the
   discrete elliptic equation A_ie u = -A_i v gives -A_i v - A_i u =
   -(lambda/(1+lambda)) A_i v.
+* The elliptic equation (Algorithm 2's first box): residual, zero lumped
+  mean, conservation; reduction to the anisotropic monodomain for
+  proportional tensors; per-direction effective conductivity when the
+  anisotropy ratios differ; the one-pass partitioned run equal to the
+  monodomain run for the paper's equal conductivities.
 * Physiology against printed values (tests/golden/paper_biomarkers.json): the
   planar conduction velocity at the paper's h and conductivities.
 """
@@ -138,3 +143,61 @@ def test_conduction_velocity_near_printed_value(model, window):
     else:
         cv = planar_cv(TT06, tt06.published_initial(), 22.0)
     assert window[0] * ref < cv < window[1] * ref, cv
+
+
+# ---- the elliptic equation and the partitioned step (Algorithm 2, one pass) ----------
+from oracle.diffusion import Bidomain, advance_bidomain  # noqa: E402
+
+
+def test_elliptic_solve_residual_and_mean():
+    shape, h = (9, 8, 5), 0.05
+    b = Bidomain(shape, h, [1.5e-3, 0.5e-3, 1.0e-3], [1.0e-3, 2.0e-3, 0.7e-3])
+    v = np.random.Generator(np.random.PCG64(4)).normal(size=int(np.prod(shape)))
+    u = b.elliptic(v)
+    assert np.max(np.abs(b.Aie @ u + b.Ai @ v)) < 1e-15
+    assert abs(np.dot(b.ml, u)) < 1e-16
+    I = b.current(v, u)
+    assert abs(np.dot(b.ml, I)) < 1e-12 * np.abs(b.Ai @ v).sum()
+
+
+def test_proportional_tensors_reduce_to_the_anisotropic_monodomain():
+    shape, h, lam = (8, 7, 6), 0.05, 0.6
+    si = np.array([2.0e-3, 0.8e-3, 1.1e-3])
+    b = Bidomain(shape, h, si, lam * si)
+    v = np.random.Generator(np.random.PCG64(5)).normal(size=int(np.prod(shape)))
+    Am, _, ml = assemble(shape, h, si * lam / (1.0 + lam))
+    np.testing.assert_allclose(b.current(v, b.elliptic(v)), -(Am @ v) / ml, rtol=1e-9,
+                               atol=1e-14)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_unequal_ratios_act_per_direction(axis):
+    """Anisotropy ratios differ between the domains (no monodomain exists), but
+    a field varying along one axis sees exactly that axis's
+    sigma_i sigma_e / (sigma_i + sigma_e)."""
+    shape, h = (7, 6, 5), 0.05
+    si = np.array([1.5e-3, 0.5e-3, 1.0e-3])
+    se = np.array([1.0e-3, 2.0e-3, 0.3e-3])
+    b = Bidomain(shape, h, si, se)
+    x = coords(shape, h)[axis]
+    v = np.sin(7.0 * x) + x * x
+    sm = si[axis] * se[axis] / (si[axis] + se[axis])
+    s3 = np.zeros(3)
+    s3[axis] = sm
+    Am, _, ml = assemble(shape, h, s3)
+    np.testing.assert_allclose(b.current(v, b.elliptic(v)), -(Am @ v) / ml, rtol=1e-8,
+                               atol=1e-12)
+    # and the other axes' effective conductivities differ, so the check has teeth
+    other = [si[k] * se[k] / (si[k] + se[k]) for k in range(3) if k != axis]
+    assert all(abs(o - sm) > 0.1 * sm for o in other)
+
+
+def test_partitioned_step_with_equal_ratios_is_the_monodomain_run():
+    shape, h = (12, 9, 1), 0.01
+    n = int(np.prod(shape))
+    X0 = np.tile(rest.lr91_rest()[:, None], (1, n))
+    stim = np.where(np.arange(n) % shape[0] < 2, -100.0, 0.0)
+    kw = dict(dt=0.02, n_steps=15, n_nodes=3, n_sweeps=2, i_stim=stim, stim_on=0.0, stim_off=1.0)
+    a, u, _ = advance_bidomain(LR91, X0, Bidomain(shape, h, [1.5e-3] * 3, [1.5e-3] * 3), **kw)
+    b, _ = advance_coupled(LR91, X0, Diffusion(shape, h, 0.75e-3), **kw)
+    assert np.max(np.abs(a - b) / np.maximum(np.abs(b), LR91.newton_scale[:, None])) < 1e-11
