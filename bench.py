@@ -61,7 +61,8 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-SHORT_FLAGS = ("--no-serving", "--no-cpu", "--no-ros2", "--no-rl", "--no-diffusion")
+SHORT_FLAGS = ("--no-serving", "--no-cpu", "--no-ros2", "--no-rl", "--no-diffusion",
+               "--no-bidomain")
 
 
 def traffic_from_counters(fetch_csv, write_csv):
@@ -340,6 +341,52 @@ def run_reaction_diffusion(I, torch, w, steps, warmup, h=0.01, sigma=0.75e-3):
     }
 
 
+def run_bidomain(I, torch, w, n_steps=100, rtol=1e-8, max_iter=2000, h=0.01, sigma=1.5e-3):
+    """The slab with the partitioned step of Algorithm 2 (one pass per step): the
+    elliptic equation for u by Jacobi-preconditioned CG (warm start, rtol 1e-8),
+    then the current -M_L^{-1} A_i (v + u) held over one reaction step; the
+    paper's sigma_i = sigma_e = 1.5e-3 in every direction, stimulus on the first
+    five x-planes.  One untimed pass, one timed pass of n_steps steps; then the
+    time of one CG iteration from 100 iterations at rtol 0."""
+    sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
+                       newton_maxit=w.newton_maxit)
+    stim = torch.as_tensor(np.where(np.arange(w.n) % w.grid[0] < 5, -100.0, 0.0)).cuda()
+    grid = I.make_bidomain_grid(*w.grid, h=h, sigma_i=(sigma,) * 3, sigma_e=(sigma,) * 3)
+    wb = I.ionic_elliptic_work_bytes(*w.grid, max_iter)
+    work = torch.zeros(wb, dtype=torch.uint8, device="cuda")
+    u = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    idiff = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    init = sim.state.clone()
+    stream = torch.cuda.current_stream()
+
+    def one_pass():
+        sim.state.copy_(init)
+        u.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = I.reaction_bidomain_step(sim.handle, grid, 0.0, w.dt, n_steps, w.n_nodes,
+                                        w.n_sweeps, u, work, wb, idiff, stim, w.stim_t_on,
+                                        w.stim_t_off, rtol=rtol, max_iter=max_iter, stream=stream)
+        torch.cuda.synchronize()
+        return info, time.perf_counter() - t0
+
+    one_pass()
+    info, wall = one_pass()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    I.ionic_elliptic_solve(sim.handle, grid, u, work, wb, rtol=0.0, max_iter=100, stream=stream)
+    cg_iter = (time.perf_counter() - t0) / 100
+    sim.close()
+    return {
+        "steps": n_steps, "ms_per_step": wall / n_steps * 1e3,
+        "value": w.n * n_steps / wall,
+        "cg_iterations_per_step": info["cg_iterations"] / n_steps,
+        "cg_converged": info["converged"], "cg_rtol": rtol,
+        "cg_iteration_ms": cg_iter * 1e3,
+        "elliptic_share": min(1.0, info["cg_iterations"] * cg_iter / wall),
+    }
+
+
 def cpu_baseline(n_vertices=2048, n_steps=120):
     """The oracle (fp64 numpy, single thread) on a bounded sample of the workload."""
     from threadpoolctl import threadpool_limits
@@ -375,6 +422,7 @@ def main():
     ap.add_argument("--no-ros2", action="store_true")
     ap.add_argument("--no-rl", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
+    ap.add_argument("--no-bidomain", action="store_true")
     ap.add_argument("--adaptive-tol", type=float, default=1e-3)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
@@ -449,6 +497,12 @@ def main():
         print("[bench] reaction-diffusion mixed", file=sys.stderr, flush=True)
         rd = run_reaction_diffusion(I, torch, w, args.steps, args.warmup)
 
+    bido = None
+    if not args.no_bidomain:
+        w = W.c2_tt06(precision="mixed")
+        print("[bench] partitioned bidomain mixed", file=sys.stderr, flush=True)
+        bido = run_bidomain(I, torch, w)
+
     serving = None
     if not args.no_serving:
         from paper_2510_27447_amd import serve
@@ -495,6 +549,7 @@ def main():
         "ros2_sdc": ros2,
         "rush_larsen": rl,
         "reaction_diffusion": rd,
+        "bidomain": bido,
     }
     print(json.dumps(out))
 

@@ -120,6 +120,26 @@ typedef struct {
   double sigma;
 } ionic_grid;
 
+/* A structured grid with the two conductivity tensors of the bidomain model
+ * (diagonal, constant: paper section 2, "diagonal vectors with constant
+ * coefficients"; section 4 uses 1.5e-3 for every entry).  Same node layout
+ * and limits as ionic_grid.  Conductivities in cm^2/ms, per direction x, y, z. */
+typedef struct {
+  int64_t nx, ny, nz;
+  double h;
+  double sigma_i[3];
+  double sigma_e[3];
+} ionic_bidomain_grid;
+
+/* Outcome of an elliptic solve. */
+typedef struct {
+  int64_t cg_iterations;      /* iterations of the last solve (summed over steps
+                                 by reaction_bidomain_step)                        */
+  double relative_residual;   /* ||b - A_ie u|| / ||b|| of the last solve            */
+  int32_t converged;          /* 1 iff every solve reached rtol                      */
+  int32_t reserved;
+} ionic_elliptic_info;
+
 /* Outcome of reaction_sdc_adaptive. */
 typedef struct {
   double t;            /* time reached (ms); equals t_end when reached == 1       */
@@ -258,6 +278,40 @@ int reaction_diffusion_step(ionic_sim* sim, const ionic_grid* grid, double t0, d
                             int n_steps, int n_nodes, int n_sweeps, const double* i_stim_dev,
                             double stim_t_on, double stim_t_off, double* i_diff_work_dev,
                             void* hip_stream);
+
+/* Device bytes of the work buffer of ionic_elliptic_solve and
+ * reaction_bidomain_step for this grid and iteration cap (0 on bad sizes). */
+size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_iter);
+
+/* The elliptic equation of the partitioned step (section 3.1, equation
+ * semi-elliptic; section 3.3.2, Algorithm 2, first box): A_ie u = -A_i v for
+ * the current V field, A_i and A_ie the Q1 stiffness matrices of sigma_i and
+ * sigma_i + sigma_e, homogeneous Neumann boundaries.  u_dev (N doubles,
+ * device) holds the initial guess and receives the solution, whose
+ * lumped-mass mean is set to zero.  Conjugate gradients with the Jacobi
+ * preconditioner until ||b - A_ie u|| <= rtol ||b|| or max_iter iterations
+ * (not an error: info->converged = 0); reductions in a fixed order, so the
+ * result is reproducible bit for bit.  The paper uses BiCGSTAB with algebraic
+ * multigrid for this system.  work_dev: ionic_elliptic_work_bytes(...)
+ * bytes.  Synchronises hip_stream (convergence is checked every 4 iterations). */
+int ionic_elliptic_solve(ionic_sim* sim, const ionic_bidomain_grid* grid, double* u_dev,
+                         void* work_dev, size_t work_bytes, double rtol, int max_iter,
+                         ionic_elliptic_info* info, void* hip_stream);
+
+/* Partitioned bidomain stepping, one pass of Algorithm 2 per time step: u
+ * from ionic_elliptic_solve with the V field at the start of the step (warm
+ * start from u_dev), the current -M_L^{-1} A_i (v + u) into i_diff_work_dev
+ * (N doubles), held over one reaction step with the handle's predictor.  The
+ * parabolic term is explicit in time: dt <= h^2 / (2 max_k sigma_i,k) is
+ * required (IONIC_EINVAL otherwise).  With sigma_e = lambda sigma_i this is
+ * reaction_diffusion_step with the monodomain sigma.  u_dev ends with the u of
+ * the last step.  info (may be NULL) sums the iterations over the steps.
+ * Synchronises hip_stream. */
+int reaction_bidomain_step(ionic_sim* sim, const ionic_bidomain_grid* grid, double t0, double dt,
+                           int n_steps, int n_nodes, int n_sweeps, const double* i_stim_dev,
+                           double stim_t_on, double stim_t_off, double* u_dev, void* work_dev,
+                           size_t work_bytes, double rtol, int max_iter, double* i_diff_work_dev,
+                           ionic_elliptic_info* info, void* hip_stream);
 
 /* Store the step inputs of `sim` for reaction_sdc_step_batch (same meaning as
  * the arguments of reaction_sdc_step).  The batch advances the handle's own

@@ -399,6 +399,162 @@ int reaction_diffusion_step(ionic_sim* s, const ionic_grid* g, double t0, double
   return IONIC_OK;
 }
 
+size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_iter) {
+  if (nx < 1 || ny < 1 || nz < 1 || max_iter < 0 || max_iter > (1 << 24)) return 0;
+  if ((__int128)nx * ny * nz > ((__int128)1 << 36)) return 0;
+  return ionic::CgWork::bytes(nx * ny * nz, ionic::cg_blocks(nx, ny, nz), max_iter);
+}
+
+static int check_bidomain_grid(const ionic_sim* s, const ionic_bidomain_grid* g) {
+  if (!g) return fail(IONIC_EINVAL, "grid is NULL");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(IONIC_EINVAL, "grid extents must be >= 1");
+  if ((__int128)g->nx * g->ny * g->nz != (__int128)s->n)
+    return fail(IONIC_EINVAL, "grid nx*ny*nz must equal the vertex count");
+  if (g->ny > 65535 || g->nz > 65535) return fail(IONIC_EINVAL, "grid ny and nz must be <= 65535");
+  if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(IONIC_EINVAL, "grid h must be positive");
+  for (int a = 0; a < 3; ++a) {
+    if (!(g->sigma_i[a] >= 0.0) || !(g->sigma_e[a] >= 0.0) || !std::isfinite(g->sigma_i[a]) ||
+        !std::isfinite(g->sigma_e[a]))
+      return fail(IONIC_EINVAL, "conductivities must be finite and >= 0");
+    const int64_t ext = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+    if (ext > 1 && !(g->sigma_i[a] + g->sigma_e[a] > 0.0))
+      return fail(IONIC_EINVAL, "sigma_i + sigma_e must be > 0 along every grid direction");
+  }
+  return IONIC_OK;
+}
+
+// One elliptic solve on stream st (synchronises it); info accumulates.
+static int elliptic_solve_impl(ionic_sim* s, const ionic_bidomain_grid* g, double* u,
+                               void* work, size_t work_bytes, double rtol, int max_iter,
+                               ionic_elliptic_info* info, hipStream_t st) {
+  ionic::CgParams c;
+  c.nx = g->nx;
+  c.ny = g->ny;
+  c.nz = g->nz;
+  for (int a = 0; a < 3; ++a) {
+    c.si[a] = g->sigma_i[a];
+    c.sie[a] = g->sigma_i[a] + g->sigma_e[a];
+  }
+  const long long n = s->n, parts = ionic::cg_blocks(c.nx, c.ny, c.nz);
+  if (work_bytes < ionic::CgWork::bytes(n, parts, max_iter))
+    return fail(IONIC_EINVAL, "elliptic work buffer too small: need " +
+                                  std::to_string(ionic::CgWork::bytes(n, parts, max_iter)) +
+                                  " bytes");
+  double* base = static_cast<double*>(work);
+  ionic::CgWork w;
+  w.r = base;
+  w.z = w.r + n;
+  w.p = w.z + n;
+  w.q = w.p + n;
+  w.part_a = w.q + n;
+  w.part_b = w.part_a + parts;
+  w.part_c = w.part_b + parts;
+  w.sc = w.part_c + parts;
+  w.n_parts = parts;
+  const double* V = static_cast<const double*>(s->state);
+  IONIC_HIP(ionic::cg_start(c, V, u, w, st));
+  double h0[3];  // b.b, r.r at the start
+  IONIC_HIP(hipMemcpyAsync(&h0[0], w.bb(), sizeof(double), hipMemcpyDeviceToHost, st));
+  IONIC_HIP(hipMemcpyAsync(&h0[1], w.rr(0), sizeof(double), hipMemcpyDeviceToHost, st));
+  IONIC_HIP(hipStreamSynchronize(st));
+  const double bb = h0[0];
+  double rel = bb > 0.0 ? std::sqrt(h0[1] / bb) : 0.0;
+  int k = 0;
+  constexpr int kCheckEvery = 4;
+  if (bb > 0.0) {
+    while (rel > rtol && k < max_iter) {
+      const int until = std::min(max_iter, k + kCheckEvery);
+      for (; k < until; ++k) IONIC_HIP(ionic::cg_iteration(c, k, u, w, st));
+      double rr = 0.0;
+      IONIC_HIP(hipMemcpyAsync(&rr, w.rr(k), sizeof(double), hipMemcpyDeviceToHost, st));
+      IONIC_HIP(hipStreamSynchronize(st));
+      rel = std::sqrt(rr / bb);
+      if (!std::isfinite(rel)) break;
+    }
+  } else {
+    // b = 0 (a spatially constant V): u is a constant, zero after the mean
+  }
+  IONIC_HIP(ionic::cg_remove_mean(c, u, w, st));
+  IONIC_HIP(hipStreamSynchronize(st));
+  if (info) {
+    info->cg_iterations += k;
+    info->relative_residual = rel;
+    info->converged = info->converged && (bb == 0.0 || rel <= rtol) ? 1 : 0;
+  }
+  return IONIC_OK;
+}
+
+int ionic_elliptic_solve(ionic_sim* s, const ionic_bidomain_grid* g, double* u_dev,
+                         void* work_dev, size_t work_bytes, double rtol, int max_iter,
+                         ionic_elliptic_info* info, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_bidomain_grid(s, g);
+  if (rc != IONIC_OK) return rc;
+  if (!u_dev || !work_dev) return fail(IONIC_EINVAL, "u_dev or work_dev is NULL");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(IONIC_EINVAL, "rtol must be >= 0");
+  if (max_iter < 0 || max_iter > (1 << 24)) return fail(IONIC_EINVAL, "max_iter out of range");
+  ionic_elliptic_info local{0, 0.0, 1, 0};
+  rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &local,
+                           static_cast<hipStream_t>(hip_stream));
+  if (rc != IONIC_OK) return rc;
+  if (info) *info = local;
+  return IONIC_OK;
+}
+
+int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0, double dt,
+                           int n_steps, int n_nodes, int n_sweeps, const double* i_stim_dev,
+                           double stim_t_on, double stim_t_off, double* u_dev, void* work_dev,
+                           size_t work_bytes, double rtol, int max_iter, double* i_diff_work_dev,
+                           ionic_elliptic_info* info, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_bidomain_grid(s, g);
+  if (rc != IONIC_OK) return rc;
+  rc = check_step_args(t0, dt, n_steps, n_nodes, n_sweeps, stim_t_on, stim_t_off);
+  if (rc != IONIC_OK) return rc;
+  if (!u_dev || !work_dev || !i_diff_work_dev)
+    return fail(IONIC_EINVAL, "u_dev, work_dev or i_diff_work_dev is NULL");
+  if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(IONIC_EINVAL, "rtol must be >= 0");
+  if (max_iter < 0 || max_iter > (1 << 24)) return fail(IONIC_EINVAL, "max_iter out of range");
+  double smax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const int64_t ext = a == 0 ? g->nx : (a == 1 ? g->ny : g->nz);
+    if (ext > 1) smax = std::max(smax, g->sigma_i[a]);
+  }
+  if (dt * smax * 4.0 / (g->h * g->h) > 2.0)
+    return fail(IONIC_EINVAL, "explicit parabolic term unstable: dt must be <= h^2 / (2 max sigma_i) = " +
+                                  std::to_string(g->h * g->h / (2.0 * smax)));
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  ionic::CgParams c;
+  c.nx = g->nx;
+  c.ny = g->ny;
+  c.nz = g->nz;
+  for (int a = 0; a < 3; ++a) {
+    c.si[a] = g->sigma_i[a];
+    c.sie[a] = g->sigma_i[a] + g->sigma_e[a];
+  }
+  LaunchCommon lc;
+  fill_quadrature(n_nodes, lc);
+  lc.tol = s->tol;
+  lc.maxit = s->maxit;
+  lc.n_sims = 1;
+  const int blocks = int((s->n + kBlock - 1) / kBlock);
+  const ionic::SdcLaunch launch = s->ops->sdc[s->precision][s->predictor];
+  ionic_elliptic_info acc{0, 0.0, 1, 0};
+  for (int k = 0; k < n_steps; ++k) {
+    rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &acc, st);
+    if (rc != IONIC_OK) return rc;
+    IONIC_HIP(ionic::bidomain_current(c, static_cast<const double*>(s->state), u_dev, g->h,
+                                      i_diff_work_dev, st));
+    lc.sims[0] = desc_of(s, t0, dt, i_stim_dev, stim_t_on, stim_t_off, i_diff_work_dev, k, 1,
+                         n_sweeps, 0);
+    hipError_t e = launch(n_nodes, s->params(), lc, blocks, st);
+    if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (bidomain)");
+  }
+  IONIC_HIP(hipStreamSynchronize(st));
+  if (info) *info = acc;
+  return IONIC_OK;
+}
+
 int ionic_set_predictor(ionic_sim* s, int predictor) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
   if (predictor != IONIC_PRED_NEWTON && predictor != IONIC_PRED_ROS2 &&

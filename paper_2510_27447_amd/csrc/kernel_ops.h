@@ -66,6 +66,38 @@ hipError_t lr91_sdc_mixed_rl(int, const void*, const LaunchCommon&, int, hipStre
 hipError_t diffusion_launch(const double* V, long long nx, long long ny, long long nz, double h,
                             double sigma, double* out, hipStream_t st);
 
+// Elliptic equation A_ie u = -A_i v by Jacobi-preconditioned conjugate
+// gradients and the current -M_L^{-1} A_i (v + u) (elliptic.hip).
+struct CgParams {
+  long long nx, ny, nz;
+  double si[3];   // sigma_i per direction
+  double sie[3];  // sigma_i + sigma_e per direction
+};
+// Work vectors and scalars of one solve, carved from one device buffer.
+// Scalars: [0] b.b, [1], [2] the lumped-mass sums of the mean, then from
+// index 8 the triple (r.z, p.q, r.r) of every iteration k.
+struct CgWork {
+  double *r, *z, *p, *q;             // n each
+  double *part_a, *part_b, *part_c;  // one partial sum per block each
+  double* sc;
+  long long n_parts;
+  double* bb() { return sc; }
+  double* mean_sums() { return sc + 1; }
+  double* rz(int k) { return sc + 8 + 3 * k; }
+  double* pq(int k) { return sc + 8 + 3 * k + 1; }
+  double* rr(int k) { return sc + 8 + 3 * k + 2; }
+  static size_t bytes(long long n, long long n_parts, int max_iter) {
+    return sizeof(double) * size_t(4 * n + 3 * n_parts + 8 + 3 * (max_iter + 2));
+  }
+};
+long long cg_blocks(long long nx, long long ny, long long nz);
+hipError_t cg_start(const CgParams& c, const double* V, const double* U, CgWork& w,
+                    hipStream_t st);
+hipError_t cg_iteration(const CgParams& c, int k, double* U, CgWork& w, hipStream_t st);
+hipError_t cg_remove_mean(const CgParams& c, double* U, CgWork& w, hipStream_t st);
+hipError_t bidomain_current(const CgParams& c, const double* V, const double* U, double h,
+                            double* out, hipStream_t st);
+
 // Adaptive step control (control.hip).
 hipError_t adapt_init(AdaptCtl* c, ErrSlot* err, double t0, double t_end, double dt_init,
                       double dt_max, double tol, double dt_min, double t_on, double t_off,

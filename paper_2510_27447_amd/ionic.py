@@ -72,6 +72,25 @@ class ionic_grid(ctypes.Structure):
                 ("sigma", c_double)]
 
 
+class ionic_bidomain_grid(ctypes.Structure):
+    _fields_ = [("nx", c_int64), ("ny", c_int64), ("nz", c_int64), ("h", c_double),
+                ("sigma_i", c_double * 3), ("sigma_e", c_double * 3)]
+
+
+class ionic_elliptic_info(ctypes.Structure):
+    _fields_ = [("cg_iterations", c_int64), ("relative_residual", c_double),
+                ("converged", c_int32), ("reserved", c_int32)]
+
+
+def make_bidomain_grid(nx, ny=1, nz=1, h=0.01, sigma_i=(1.5e-3,) * 3, sigma_e=(1.5e-3,) * 3):
+    g = ionic_bidomain_grid()
+    g.nx, g.ny, g.nz, g.h = int(nx), int(ny), int(nz), float(h)
+    for a in range(3):
+        g.sigma_i[a] = float(sigma_i[a])
+        g.sigma_e[a] = float(sigma_e[a])
+    return g
+
+
 def make_grid(nx, ny=1, nz=1, h=0.01, sigma=0.75e-3):
     g = ionic_grid()
     g.nx, g.ny, g.nz, g.h, g.sigma = int(nx), int(ny), int(nz), float(h), float(sigma)
@@ -101,6 +120,14 @@ _SIGNATURES = {
     "reaction_diffusion_step": (c_int, [c_void_p, POINTER(ionic_grid), c_double, c_double, c_int,
                                         c_int, c_int, c_void_p, c_double, c_double, c_void_p,
                                         c_void_p]),
+    "ionic_elliptic_work_bytes": (c_size_t, [c_int64, c_int64, c_int64, c_int]),
+    "ionic_elliptic_solve": (c_int, [c_void_p, POINTER(ionic_bidomain_grid), c_void_p, c_void_p,
+                                     c_size_t, c_double, c_int, POINTER(ionic_elliptic_info),
+                                     c_void_p]),
+    "reaction_bidomain_step": (c_int, [c_void_p, POINTER(ionic_bidomain_grid), c_double, c_double,
+                                       c_int, c_int, c_int, c_void_p, c_double, c_double,
+                                       c_void_p, c_void_p, c_size_t, c_double, c_int, c_void_p,
+                                       POINTER(ionic_elliptic_info), c_void_p]),
     "ionic_set_inputs": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_void_p, c_double,
                                  c_double, c_void_p]),
     "reaction_sdc_step_batch": (c_int, [POINTER(c_void_p), POINTER(c_int), c_int, c_void_p]),
@@ -271,6 +298,34 @@ def reaction_diffusion_step(handle, grid, t0, dt, n_steps, n_nodes, n_sweeps, wo
     _check(lib().reaction_diffusion_step(handle, ctypes.byref(grid), t0, dt, n_steps, n_nodes,
                                          n_sweeps, _ptr(i_stim), stim_t_on, stim_t_off, _ptr(work),
                                          _stream(stream)))
+
+
+def ionic_elliptic_work_bytes(nx, ny, nz, max_iter):
+    return lib().ionic_elliptic_work_bytes(nx, ny, nz, max_iter)
+
+
+def _info_dict(info):
+    return {name: getattr(info, name) for name, _ in ionic_elliptic_info._fields_
+            if name != "reserved"}
+
+
+def ionic_elliptic_solve(handle, grid, u, work, work_bytes, rtol=1e-8, max_iter=1000,
+                         stream=None):
+    info = ionic_elliptic_info()
+    _check(lib().ionic_elliptic_solve(handle, ctypes.byref(grid), _ptr(u), _ptr(work), work_bytes,
+                                      rtol, max_iter, ctypes.byref(info), _stream(stream)))
+    return _info_dict(info)
+
+
+def reaction_bidomain_step(handle, grid, t0, dt, n_steps, n_nodes, n_sweeps, u, work, work_bytes,
+                           i_diff_work, i_stim=None, stim_t_on=0.0, stim_t_off=0.0, rtol=1e-8,
+                           max_iter=1000, stream=None):
+    info = ionic_elliptic_info()
+    _check(lib().reaction_bidomain_step(handle, ctypes.byref(grid), t0, dt, n_steps, n_nodes,
+                                        n_sweeps, _ptr(i_stim), stim_t_on, stim_t_off, _ptr(u),
+                                        _ptr(work), work_bytes, rtol, max_iter, _ptr(i_diff_work),
+                                        ctypes.byref(info), _stream(stream)))
+    return _info_dict(info)
 
 
 def ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0,

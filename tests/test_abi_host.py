@@ -145,3 +145,17 @@ def test_diffusion_entry_points_reject_bad_arguments():
     assert lib.ionic_diffusion_current(None, I.ctypes.byref(g), None, None) == -1
     assert lib.reaction_diffusion_step(None, I.ctypes.byref(g), 0.0, 0.02, 1, 3, 2, None, 0.0,
                                        0.0, None, None) == -1
+
+
+def test_elliptic_work_bytes_and_rejections():
+    n, parts = 100 * 100 * 100, 2 * 100 * 100
+    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (4 * n + 3 * parts + 8 + 3 * 52)
+    assert I.ionic_elliptic_work_bytes(0, 1, 1, 10) == 0
+    assert I.ionic_elliptic_work_bytes(10, 1, 1, -1) == 0
+    lib = I.lib()
+    g = I.make_bidomain_grid(10)
+    info = I.ionic_elliptic_info()
+    assert lib.ionic_elliptic_solve(None, I.ctypes.byref(g), None, None, 0, 1e-8, 10,
+                                    I.ctypes.byref(info), None) == -1
+    assert lib.reaction_bidomain_step(None, I.ctypes.byref(g), 0.0, 0.02, 1, 3, 2, None, 0.0, 0.0,
+                                      None, None, 0, 1e-8, 10, None, None, None) == -1
