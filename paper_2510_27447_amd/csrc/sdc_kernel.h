@@ -378,7 +378,11 @@ __global__ void __launch_bounds__(kBlock)
           y += TE(kRosM1) * u1[i] + TE(kRosM2) * u2[i];
           const TE ay = fabs(TE(y));
           const TE sc = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
-          const TE e = fabs(TE(kRosM2) * (u1[i] + u2[i])) / sc;
+          // fp32: the hardware reciprocal (1 ulp) in place of an IEEE division;
+          // fp64 keeps the exact quotient
+          const TE num = fabs(TE(kRosM2) * (u1[i] + u2[i]));
+          TE e;
+          if constexpr (sizeof(TE) == 4) e = num * f_rcp(sc); else e = num / sc;
           err_est = (e > err_est || e != e) ? e : err_est;
         });
       });
@@ -418,7 +422,7 @@ __global__ void __launch_bounds__(kBlock)
           SinkCore<Model, TE, decltype(bfn)> s(dtau[m], bfn);
           call_rhs_masked<Model, TE, CORE>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
           s.solve(delta);
-          TE err = TE(0);
+          bool now_conv = true;  // |delta_i| <= tol s_i over the core
           static_for<NC>([&](auto I) {
             constexpr int i = I;
             auto& y = L::template at<i>(Y);
@@ -426,10 +430,8 @@ __global__ void __launch_bounds__(kBlock)
             y = pick(run, yn, y);
             const TE ay = fabs(TE(yn));
             const TE sc = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
-            const TE e = fabs(delta[i]) / sc;
-            err = e > err ? e : err;
+            now_conv &= fabs(delta[i]) <= tol * sc;
           });
-          const bool now_conv = err <= tol;
           it += int(run);
           conv = (run & now_conv) | (!run & conv);
           run = run & !conv & (it < args.maxit);
@@ -467,7 +469,9 @@ __global__ void __launch_bounds__(kBlock)
           ++pass;
           // every quantity below is computed on all lanes and only chosen per
           // lane, with no conditional evaluation, so no divergent branch forms
-          TE err = TE(0);
+          // stop test max_i |delta_i| / s_i <= tol, written as |delta_i| <= tol s_i
+          // for every i (no division)
+          bool now_conv = true;
           static_for<N>([&](auto I) {
             constexpr int i = I;
             auto& y = L::template at<i>(Y);
@@ -475,10 +479,8 @@ __global__ void __launch_bounds__(kBlock)
             y = pick(run, yn, y);
             const TE ay = fabs(TE(yn));
             const TE s = ay > TE(Model::SCALE[i]) ? ay : TE(Model::SCALE[i]);
-            const TE e = fabs(delta[i]) / s;
-            err = e > err ? e : err;
+            now_conv &= fabs(delta[i]) <= tol * s;
           });
-          const bool now_conv = err <= tol;
           it += int(run);
           conv = (run & now_conv) | (!run & conv);
           run = run & !conv & (it < args.maxit);
