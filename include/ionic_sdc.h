@@ -107,9 +107,9 @@ typedef struct {
 
 /* A structured grid of nodes for the diffusion current (paper section 3.1:
  * Q1 elements on quadrilaterals / hexahedra).  Vertex index i + nx*(j + ny*k),
- * x fastest; nx*ny*nz must equal the simulation's vertex count, ny and nz
- * at most 65535; an extent of 1 drops that direction (1D cables, 2D sheets).  h: node spacing in cm,
- * uniform.  sigma: the conductivity in the voltage equation, cm^2/ms (for the
+ * x fastest; nx*ny*nz must equal the simulation's vertex count and be below
+ * 2^31; an extent of 1 drops that direction (1D cables, 2D sheets).  h: node
+ * spacing in cm, uniform.  sigma: the conductivity in the voltage equation, cm^2/ms (for the
  * paper's bidomain with sigma_e = lambda sigma_i this is the monodomain
  * sigma_i sigma_e/(sigma_i + sigma_e): the elliptic solve then gives
  * -A_i v - A_i u = -(lambda/(1+lambda)) A_i v exactly; 0.75e-3 for
@@ -121,8 +121,8 @@ typedef struct {
 } ionic_grid;
 
 /* A structured grid with the two conductivity tensors of the bidomain model
- * (diagonal, constant: paper section 2, "diagonal vectors with constant
- * coefficients"; section 4 uses 1.5e-3 for every entry).  Same node layout
+ * (diagonal and constant in space, as in paper section 2; section 4 uses
+ * 1.5e-3 for every entry).  Same node layout
  * and limits as ionic_grid.  Conductivities in cm^2/ms, per direction x, y, z. */
 typedef struct {
   int64_t nx, ny, nz;
@@ -290,10 +290,13 @@ size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_ite
  * device) holds the initial guess and receives the solution, whose
  * lumped-mass mean is set to zero.  Conjugate gradients with the Jacobi
  * preconditioner until ||b - A_ie u|| <= rtol ||b|| or max_iter iterations
- * (not an error: info->converged = 0); reductions in a fixed order, so the
- * result is reproducible bit for bit.  The paper uses BiCGSTAB with algebraic
- * multigrid for this system.  work_dev: ionic_elliptic_work_bytes(...)
- * bytes.  Synchronises hip_stream (convergence is checked every 4 iterations). */
+ * (not an error: info->converged = 0); info->cg_iterations is the first
+ * iteration count that meets rtol (the test runs on the device after every
+ * iteration).  Reductions in a fixed order, so the result is reproducible bit
+ * for bit.  The paper uses BiCGSTAB with algebraic multigrid for this system.
+ * work_dev: ionic_elliptic_work_bytes(...) bytes, not shared with a solve
+ * running at the same time.  Synchronises hip_stream (the host reads the
+ * device's convergence flag between batches of iteration launches). */
 int ionic_elliptic_solve(ionic_sim* sim, const ionic_bidomain_grid* grid, double* u_dev,
                          void* work_dev, size_t work_bytes, double rtol, int max_iter,
                          ionic_elliptic_info* info, void* hip_stream);

@@ -13,12 +13,26 @@
 // conjugate gradients with the Jacobi preconditioner, warm-started from the
 // previous step's u.
 //
-// Every kernel runs one thread per node on a 3D launch (64 threads along x).
-// Dot products are reduced deterministically: each block writes one partial
-// sum (a fixed butterfly over its wavefront), and reduce_kernel sums the
-// partials in a fixed order, so a solve gives the same bits every time.  The
-// scalars of iteration k live at their own addresses (rz[k], pq[k], rr[k]),
-// so no kernel writes a scalar that another block of the same launch reads.
+// Launch shape: nb blocks of 256 threads (nb a multiple of 8, at most 1024);
+// block L owns the nodes [L chunk, (L + 1) chunk), its threads stride through
+// them.  Blocks are dispatched to the 8 XCDs in turn (block b to XCD b mod 8),
+// so block b takes the chunk L = (b mod 8) nb/8 + b/8: each XCD works on one
+// contiguous eighth of the grid, and the stencil's neighbours (one x-row or
+// one xy-plane away) mostly sit in the same XCD's L2.
+//
+// Dot products are reduced in a fixed order and without any synchronisation
+// between blocks: each block sums its threads (wavefront butterfly, then its 4
+// wavefronts in order) into its own slot, and every block of the next launch
+// that needs the total adds the nb slots itself, in the same fixed order, so
+// all blocks get the same bits and a solve is reproducible bit for bit.  The
+// kernels that consume a total also record it (block 0) in the scalars of
+// iteration k (rz[k], pq[k], rr[k]).
+//
+// An iteration is two launches: cg_q_kernel (direction and q = A_ie p) and
+// cg_update_kernel (u, r, z).  The first launch of iteration k adds the r.r
+// slots of iteration k-1 and tests ||r_k|| <= rtol ||b||: done is set there,
+// after which every queued launch returns at once; the host only reads the
+// flag between batches of launches.
 #include "kernel_ops.h"
 #include "stencil.h"
 
@@ -26,210 +40,305 @@ namespace ionic {
 
 namespace {
 
-constexpr int kBlk = 64;
-constexpr int kRedBlock = 256;
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxBlocks = 1024;
+constexpr int kXcds = 8;
 
 __device__ __forceinline__ double wave_sum_d(double x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
 }
 
-struct Launch3 {
-  long long nx, ny, nz;
-  __device__ __forceinline__ long long block_id() const {
-    const long long gx = (nx + kBlk - 1) / kBlk;
-    return blockIdx.x + gx * ((long long)blockIdx.y + ny * (long long)blockIdx.z);
-  }
-};
-
-__device__ __forceinline__ void put_partial(double a, double* part, long long bid) {
-  const double s = wave_sum_d(a);
-  if (threadIdx.x == 0) part[bid] = s;
+// chunk owned by this block (see the launch shape above)
+__device__ __forceinline__ long long chunk_id(const CgParams& c) {
+  const long long b = blockIdx.x;
+  return (b % kXcds) * (c.nb / kXcds) + b / kXcds;
 }
 
-__global__ void __launch_bounds__(kBlk)
+// Sum of each of NV per-thread values over the block, fixed order; the totals
+// in every thread.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV]) {
+  __shared__ double lds[NV][kWaves];
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = wave_sum_d(v[a]);
+  __syncthreads();  // a previous call's readers are done with lds
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int a = 0; a < NV; ++a) lds[a][threadIdx.x >> 6] = v[a];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < NV; ++a) v[a] = (lds[a][0] + lds[a][1]) + (lds[a][2] + lds[a][3]);
+}
+
+// this block's sums into slot chunk_id of part[a]
+template <int NV>
+__device__ __forceinline__ void put_partials(double (&v)[NV], double* const (&part)[NV],
+                                             const CgParams& c) {
+  block_sum(v);
+  if (threadIdx.x == 0) {
+    const long long L = chunk_id(c);
+#pragma unroll
+    for (int a = 0; a < NV; ++a) part[a][L] = v[a];
+  }
+}
+
+// totals of the nb slots of each part[a] (written by an earlier launch), the
+// same fixed order in every block; the totals in every thread
+template <int NV>
+__device__ __forceinline__ void total_of(const double* const (&part)[NV], const CgParams& c,
+                                         double (&s)[NV]) {
+#pragma unroll
+  for (int a = 0; a < NV; ++a) s[a] = 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxBlocks / kThreads; ++j) {
+    const long long t = threadIdx.x + (long long)j * kThreads;
+    if (t < c.nb) {
+#pragma unroll
+      for (int a = 0; a < NV; ++a) s[a] += part[a][t];
+    }
+  }
+  block_sum(s);
+}
+
+// convergence after iteration k from r.r and b.b (the host's test)
+__device__ __forceinline__ bool converged(const CgParams& c, double rr, double bb) {
+  const double rel = bb > 0.0 ? ::sqrt(rr / bb) : 0.0;
+  return !(rel > c.rtol) || ::isinf(rel);
+}
+
+// this thread's first node and the end of the block's chunk; the thread takes
+// every kThreads-th node from first
+struct Nodes {
+  long long first, end;
+};
+__device__ __forceinline__ Nodes my_nodes(const CgParams& c) {
+  const long long begin = chunk_id(c) * c.chunk, end = begin + c.chunk;
+  return {begin + threadIdx.x, end < c.n ? end : c.n};
+}
+
+__global__ void __launch_bounds__(kThreads)
     cg_start_kernel(const double* __restrict__ V, const double* __restrict__ U, CgParams c,
-                    double* __restrict__ r, double* __restrict__ z, double* __restrict__ p,
-                    double* __restrict__ part_a, double* __restrict__ part_b,
-                    double* __restrict__ part_c) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  const bool on = i < c.nx;
-  double rz = 0.0, bb = 0.0, rr = 0.0;
-  if (on) {
-    const Q1Node node(i, blockIdx.y, blockIdx.z, c.nx, c.ny, c.nz);
-    const long long n = node.index();
+                    CgWork w) {
+  double s[3] = {0.0, 0.0, 0.0};  // r.z, b.b, r.r
+  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
+    const Q1Coords x = q1_coords(v, c.nx, c.ny);
+    const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
     const double b = -node.apply(V, c.si);
     const double rn = b - node.apply(U, c.sie);
     const double zn = rn / node.diag(c.sie);
-    r[n] = rn;
-    z[n] = zn;
-    p[n] = zn;
-    rz = rn * zn;
-    bb = b * b;
-    rr = rn * rn;
+    w.r[v] = rn;
+    w.z[v] = zn;
+    w.p_k(-1)[v] = 0.0;  // p_0 = z_0
+    s[0] += rn * zn;
+    s[1] += b * b;
+    s[2] += rn * rn;
   }
-  const long long bid = Launch3{c.nx, c.ny, c.nz}.block_id();
-  put_partial(rz, part_a, bid);
-  put_partial(bb, part_b, bid);
-  put_partial(rr, part_c, bid);
+  double* const part[3] = {w.part_a, w.part_b, w.part_c};
+  put_partials(s, part, c);
 }
 
-__global__ void __launch_bounds__(kBlk)
-    cg_q_kernel(const double* __restrict__ p, CgParams c, double* __restrict__ q,
-                double* __restrict__ part_a) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  double pq = 0.0;
-  if (i < c.nx) {
-    const Q1Node node(i, blockIdx.y, blockIdx.z, c.nx, c.ny, c.nz);
-    const long long n = node.index();
-    const double qn = node.apply(p, c.sie);
-    q[n] = qn;
-    pq = p[n] * qn;
+// one block: the scalars of the start and the test before the first iteration
+__global__ void __launch_bounds__(kThreads) cg_start_sums_kernel(CgParams c, CgWork w) {
+  const double* const part[3] = {w.part_a, w.part_b, w.part_c};
+  double s[3];
+  total_of(part, c, s);
+  if (threadIdx.x == 0) {
+    *w.rz(0) = s[0];
+    *w.bb() = s[1];
+    *w.rr(0) = s[2];
+    CgCtl* ctl = w.ctl();
+    ctl->done = converged(c, s[2], s[1]) ? 1 : 0;
+    ctl->reserved = 0;
+    ctl->iters = 0;
   }
-  put_partial(pq, part_a, Launch3{c.nx, c.ny, c.nz}.block_id());
 }
 
-__global__ void __launch_bounds__(kBlk)
-    cg_update_kernel(CgParams c, const double* __restrict__ rz_k, const double* __restrict__ pq_k,
-                     double* __restrict__ U, double* __restrict__ r, double* __restrict__ z,
-                     const double* __restrict__ p, const double* __restrict__ q,
-                     double* __restrict__ part_a, double* __restrict__ part_b) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  const double pq = *pq_k;
-  const double alpha = pq != 0.0 ? *rz_k / pq : 0.0;
-  double rz = 0.0, rr = 0.0;
-  if (i < c.nx) {
-    const Q1Node node(i, blockIdx.y, blockIdx.z, c.nx, c.ny, c.nz);
-    const long long n = node.index();
-    U[n] += alpha * p[n];
-    const double rn = r[n] - alpha * q[n];
+// Iteration k, first launch: the direction p_k = z_k + beta_k p_(k-1) and
+// q = A_ie p_k, with the block's part of p_k.q.  For k > 0 the block first adds
+// the slots of r.z and r.r left by iteration k-1 (beta_k = r_k.z_k /
+// r_(k-1).z_(k-1)) and stops the solve if ||r_k|| meets the tolerance.  p_k is
+// formed where it is used: the stencil reads z and p_(k-1) (two buffers, p_k
+// goes to the other one), so no separate direction pass is needed.  Each
+// wavefront takes 62 consecutive nodes per pass (lanes 1..62; lanes 0 and 63
+// hold the nodes on either side) so the x-neighbours come from adjacent lanes
+// (Q1Node::apply_lanes): 9 rows per node instead of 27 values.
+constexpr int kLanesOut = 62;
+
+__global__ void __launch_bounds__(kThreads) cg_q_kernel(CgParams c, CgWork w, long long k) {
+  if (w.ctl()->done) return;
+  double beta = 0.0;
+  if (k > 0) {
+    const double* const in[2] = {w.part_b, w.part_c};
+    double t[2];  // r_k.z_k, r_k.r_k
+    total_of(in, c, t);
+    const bool stop = converged(c, t[1], *w.bb());
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      *w.rz(k) = t[0];
+      *w.rr(k) = t[1];
+      if (stop) {
+        w.ctl()->iters = k;
+        w.ctl()->done = 1;
+      }
+    }
+    if (stop) return;
+    const double rz = *w.rz(k - 1);
+    beta = rz != 0.0 ? t[0] / rz : 0.0;
+  }
+  const double* __restrict__ z = w.z;
+  const double* __restrict__ p_old = w.p_k(k - 1);
+  double* __restrict__ p_new = w.p_k(k);
+  const auto p_of = [=](long long t) { return z[t] + beta * p_old[t]; };
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long begin = chunk_id(c) * c.chunk;
+  const long long end = begin + c.chunk < c.n ? begin + c.chunk : c.n;
+  double s[1] = {0.0};  // p.q
+  // the trip count is the same for every lane of a wavefront
+  for (long long first = begin + wave * kLanesOut; first < end; first += kWaves * kLanesOut) {
+    const long long v = first - 1 + lane;
+    const long long vl = v < 0 ? 0 : (v < c.n ? v : c.n - 1);  // the node this lane loads
+    const Q1Coords x = q1_coords(vl, c.nx, c.ny);
+    const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
+    double pn;
+    const double qn = node.apply_lanes(p_of, c.sie, pn);
+    if (lane >= 1 && lane <= kLanesOut && v < end) {
+      p_new[v] = pn;
+      w.q[v] = qn;
+      s[0] += pn * qn;
+    }
+  }
+  double* const part[1] = {w.part_a};
+  put_partials(s, part, c);
+}
+
+__global__ void __launch_bounds__(kThreads)
+    cg_update_kernel(CgParams c, CgWork w, long long k, double* __restrict__ U) {
+  if (w.ctl()->done) return;
+  const double* const in[1] = {w.part_a};
+  double pq[1];
+  total_of(in, c, pq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *w.pq(k) = pq[0];
+  const double alpha = pq[0] != 0.0 ? *w.rz(k) / pq[0] : 0.0;
+  const double* __restrict__ p = w.p_k(k);
+  double s[2] = {0.0, 0.0};  // r.z, r.r
+  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
+    const Q1Coords x = q1_coords(v, c.nx, c.ny);
+    const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
+    U[v] += alpha * p[v];
+    const double rn = w.r[v] - alpha * w.q[v];
     const double zn = rn / node.diag(c.sie);
-    r[n] = rn;
-    z[n] = zn;
-    rz = rn * zn;
-    rr = rn * rn;
+    w.r[v] = rn;
+    w.z[v] = zn;
+    s[0] += rn * zn;
+    s[1] += rn * rn;
   }
-  const long long bid = Launch3{c.nx, c.ny, c.nz}.block_id();
-  put_partial(rz, part_a, bid);
-  put_partial(rr, part_b, bid);
+  double* const part[2] = {w.part_b, w.part_c};
+  put_partials(s, part, c);
 }
 
-__global__ void __launch_bounds__(kBlk)
-    cg_dir_kernel(CgParams c, const double* __restrict__ rz_k, const double* __restrict__ rz_k1,
-                  const double* __restrict__ z, double* __restrict__ p) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  if (i >= c.nx) return;
-  const double rz = *rz_k;
-  const double beta = rz != 0.0 ? *rz_k1 / rz : 0.0;
-  const long long n = i + c.nx * ((long long)blockIdx.y + c.ny * (long long)blockIdx.z);
-  p[n] = z[n] + beta * p[n];
-}
-
-__global__ void __launch_bounds__(kBlk)
-    mean_parts_kernel(const double* __restrict__ U, CgParams c, double* __restrict__ part_a,
-                      double* __restrict__ part_b) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  double mu = 0.0, m = 0.0;
-  if (i < c.nx) {
-    const Q1Node node(i, blockIdx.y, blockIdx.z, c.nx, c.ny, c.nz);
-    m = node.mass();
-    mu = m * U[node.index()];
+// one block, after the last iteration launch k_end when the solve has not
+// stopped: the scalars and the test after iteration k_end
+__global__ void __launch_bounds__(kThreads) cg_end_sums_kernel(CgParams c, CgWork w,
+                                                               long long k_end) {
+  if (w.ctl()->done) return;
+  const double* const in[2] = {w.part_b, w.part_c};
+  double t[2];
+  total_of(in, c, t);
+  if (threadIdx.x == 0) {
+    *w.rz(k_end) = t[0];
+    *w.rr(k_end) = t[1];
+    if (converged(c, t[1], *w.bb())) {
+      w.ctl()->iters = k_end;
+      w.ctl()->done = 1;
+    }
   }
-  const long long bid = Launch3{c.nx, c.ny, c.nz}.block_id();
-  put_partial(mu, part_a, bid);
-  put_partial(m, part_b, bid);
 }
 
-__global__ void __launch_bounds__(kBlk)
-    sub_mean_kernel(CgParams c, const double* __restrict__ sums, double* __restrict__ U) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  if (i >= c.nx) return;
-  const double mean = sums[0] / sums[1];
-  U[i + c.nx * ((long long)blockIdx.y + c.ny * (long long)blockIdx.z)] -= mean;
+__global__ void __launch_bounds__(kThreads)
+    mean_parts_kernel(const double* __restrict__ U, CgParams c, CgWork w) {
+  double s[2] = {0.0, 0.0};  // sum m u, sum m
+  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
+    const Q1Coords x = q1_coords(v, c.nx, c.ny);
+    const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
+    const double m = node.mass();
+    s[0] += m * U[v];
+    s[1] += m;
+  }
+  double* const part[2] = {w.part_a, w.part_b};
+  put_partials(s, part, c);
 }
 
-__global__ void __launch_bounds__(kBlk)
+__global__ void __launch_bounds__(kThreads)
+    sub_mean_kernel(CgParams c, CgWork w, double* __restrict__ U) {
+  const double* const in[2] = {w.part_a, w.part_b};
+  double t[2];
+  total_of(in, c, t);
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    w.mean_sums()[0] = t[0];
+    w.mean_sums()[1] = t[1];
+  }
+  const double mean = t[0] / t[1];
+  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads)
+    U[v] -= mean;
+}
+
+__global__ void __launch_bounds__(kThreads)
     bidomain_current_kernel(const double* __restrict__ V, const double* __restrict__ U, CgParams c,
                             double inv_h2, double* __restrict__ out) {
-  const long long i = (long long)blockIdx.x * kBlk + threadIdx.x;
-  if (i >= c.nx) return;
-  const Q1Node node(i, blockIdx.y, blockIdx.z, c.nx, c.ny, c.nz);
-  out[node.index()] = -inv_h2 * (node.apply(V, c.si) + node.apply(U, c.si)) / node.mass();
-}
-
-// one block: out_a = sum of a[0..n), out_b = sum of b[0..n) (b may be null),
-// in a fixed order (thread t takes t, t + 256, ...; then a tree in LDS)
-__global__ void __launch_bounds__(kRedBlock)
-    reduce_kernel(const double* __restrict__ a, const double* __restrict__ b, long long n,
-                  double* __restrict__ out_a, double* __restrict__ out_b) {
-  __shared__ double sa[kRedBlock], sb[kRedBlock];
-  double x = 0.0, y = 0.0;
-  for (long long t = threadIdx.x; t < n; t += kRedBlock) {
-    x += a[t];
-    if (b) y += b[t];
+  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
+    const Q1Coords x = q1_coords(v, c.nx, c.ny);
+    const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
+    out[v] = -inv_h2 * (node.apply(V, c.si) + node.apply(U, c.si)) / node.mass();
   }
-  sa[threadIdx.x] = x;
-  sb[threadIdx.x] = y;
-  __syncthreads();
-  for (int w = kRedBlock / 2; w > 0; w >>= 1) {
-    if (threadIdx.x < w) {
-      sa[threadIdx.x] += sa[threadIdx.x + w];
-      sb[threadIdx.x] += sb[threadIdx.x + w];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    *out_a = sa[0];
-    if (b) *out_b = sb[0];
-  }
-}
-
-dim3 grid3(const CgParams& c) {
-  return dim3(unsigned((c.nx + kBlk - 1) / kBlk), unsigned(c.ny), unsigned(c.nz));
 }
 
 }  // namespace
 
-long long cg_blocks(long long nx, long long ny, long long nz) {
-  return (nx + kBlk - 1) / kBlk * ny * nz;
+CgParams cg_params(long long nx, long long ny, long long nz) {
+  CgParams c{};
+  c.nx = nx;
+  c.ny = ny;
+  c.nz = nz;
+  c.n = nx * ny * nz;
+  const long long want = std::min<long long>(kMaxBlocks, (c.n + kThreads - 1) / kThreads);
+  c.nb = (want + kXcds - 1) / kXcds * kXcds;
+  c.chunk = (c.n + c.nb - 1) / c.nb;
+  return c;
 }
 
 hipError_t cg_start(const CgParams& c, const double* V, const double* U, CgWork& w,
                     hipStream_t st) {
-  hipLaunchKernelGGL(cg_start_kernel, grid3(c), dim3(kBlk), 0, st, V, U, c, w.r, w.z, w.p,
-                     w.part_a, w.part_b, w.part_c);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedBlock), 0, st, w.part_a, w.part_b,
-                     w.n_parts, w.rz(0), w.bb());
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedBlock), 0, st, w.part_c,
-                     (const double*)nullptr, w.n_parts, w.rr(0), (double*)nullptr);
+  hipLaunchKernelGGL(cg_start_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, V, U, c, w);
+  hipLaunchKernelGGL(cg_start_sums_kernel, dim3(1), dim3(kThreads), 0, st, c, w);
   return hipGetLastError();
 }
 
 hipError_t cg_iteration(const CgParams& c, int k, double* U, CgWork& w, hipStream_t st) {
-  hipLaunchKernelGGL(cg_q_kernel, grid3(c), dim3(kBlk), 0, st, w.p, c, w.q, w.part_a);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedBlock), 0, st, w.part_a,
-                     (const double*)nullptr, w.n_parts, w.pq(k), (double*)nullptr);
-  hipLaunchKernelGGL(cg_update_kernel, grid3(c), dim3(kBlk), 0, st, c, w.rz(k), w.pq(k), U, w.r,
-                     w.z, w.p, w.q, w.part_a, w.part_b);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedBlock), 0, st, w.part_a, w.part_b,
-                     w.n_parts, w.rz(k + 1), w.rr(k + 1));
-  hipLaunchKernelGGL(cg_dir_kernel, grid3(c), dim3(kBlk), 0, st, c, w.rz(k), w.rz(k + 1), w.z,
-                     w.p);
+  const dim3 g(unsigned(c.nb)), b(kThreads);
+  hipLaunchKernelGGL(cg_q_kernel, g, b, 0, st, c, w, (long long)k);
+  hipLaunchKernelGGL(cg_update_kernel, g, b, 0, st, c, w, (long long)k, U);
+  return hipGetLastError();
+}
+
+hipError_t cg_end(const CgParams& c, int k_end, CgWork& w, hipStream_t st) {
+  if (k_end > 0)
+    hipLaunchKernelGGL(cg_end_sums_kernel, dim3(1), dim3(kThreads), 0, st, c, w, (long long)k_end);
   return hipGetLastError();
 }
 
 hipError_t cg_remove_mean(const CgParams& c, double* U, CgWork& w, hipStream_t st) {
-  hipLaunchKernelGGL(mean_parts_kernel, grid3(c), dim3(kBlk), 0, st, U, c, w.part_a, w.part_b);
-  hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(kRedBlock), 0, st, w.part_a, w.part_b,
-                     w.n_parts, w.mean_sums(), w.mean_sums() + 1);
-  hipLaunchKernelGGL(sub_mean_kernel, grid3(c), dim3(kBlk), 0, st, c, w.mean_sums(), U);
+  const dim3 g(unsigned(c.nb)), b(kThreads);
+  hipLaunchKernelGGL(mean_parts_kernel, g, b, 0, st, U, c, w);
+  hipLaunchKernelGGL(sub_mean_kernel, g, b, 0, st, c, w, U);
   return hipGetLastError();
 }
 
 hipError_t bidomain_current(const CgParams& c, const double* V, const double* U, double h,
                             double* out, hipStream_t st) {
-  hipLaunchKernelGGL(bidomain_current_kernel, grid3(c), dim3(kBlk), 0, st, V, U, c,
-                     1.0 / (h * h), out);
+  hipLaunchKernelGGL(bidomain_current_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, V, U,
+                     c, 1.0 / (h * h), out);
   return hipGetLastError();
 }
 

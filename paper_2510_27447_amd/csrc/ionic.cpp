@@ -349,7 +349,7 @@ static int check_grid(const ionic_sim* s, const ionic_grid* g) {
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(IONIC_EINVAL, "grid extents must be >= 1");
   if ((__int128)g->nx * g->ny * g->nz != (__int128)s->n)
     return fail(IONIC_EINVAL, "grid nx*ny*nz must equal the vertex count");
-  if (g->ny > 65535 || g->nz > 65535) return fail(IONIC_EINVAL, "grid ny and nz must be <= 65535");
+  if (s->n >= (int64_t(1) << 31)) return fail(IONIC_EINVAL, "grid must have fewer than 2^31 nodes");
   if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(IONIC_EINVAL, "grid h must be positive");
   if (!(g->sigma >= 0.0) || !std::isfinite(g->sigma))
     return fail(IONIC_EINVAL, "grid sigma must be finite and >= 0");
@@ -401,8 +401,8 @@ int reaction_diffusion_step(ionic_sim* s, const ionic_grid* g, double t0, double
 
 size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_iter) {
   if (nx < 1 || ny < 1 || nz < 1 || max_iter < 0 || max_iter > (1 << 24)) return 0;
-  if ((__int128)nx * ny * nz > ((__int128)1 << 36)) return 0;
-  return ionic::CgWork::bytes(nx * ny * nz, ionic::cg_blocks(nx, ny, nz), max_iter);
+  if ((__int128)nx * ny * nz >= ((__int128)1 << 31)) return 0;
+  return ionic::CgWork::bytes(nx * ny * nz, ionic::cg_params(nx, ny, nz).nb, max_iter);
 }
 
 static int check_bidomain_grid(const ionic_sim* s, const ionic_bidomain_grid* g) {
@@ -410,7 +410,7 @@ static int check_bidomain_grid(const ionic_sim* s, const ionic_bidomain_grid* g)
   if (g->nx < 1 || g->ny < 1 || g->nz < 1) return fail(IONIC_EINVAL, "grid extents must be >= 1");
   if ((__int128)g->nx * g->ny * g->nz != (__int128)s->n)
     return fail(IONIC_EINVAL, "grid nx*ny*nz must equal the vertex count");
-  if (g->ny > 65535 || g->nz > 65535) return fail(IONIC_EINVAL, "grid ny and nz must be <= 65535");
+  if (s->n >= (int64_t(1) << 31)) return fail(IONIC_EINVAL, "grid must have fewer than 2^31 nodes");
   if (!(g->h > 0.0) || !std::isfinite(g->h)) return fail(IONIC_EINVAL, "grid h must be positive");
   for (int a = 0; a < 3; ++a) {
     if (!(g->sigma_i[a] >= 0.0) || !(g->sigma_e[a] >= 0.0) || !std::isfinite(g->sigma_i[a]) ||
@@ -424,62 +424,69 @@ static int check_bidomain_grid(const ionic_sim* s, const ionic_bidomain_grid* g)
 }
 
 // One elliptic solve on stream st (synchronises it); info accumulates.
-static int elliptic_solve_impl(ionic_sim* s, const ionic_bidomain_grid* g, double* u,
-                               void* work, size_t work_bytes, double rtol, int max_iter,
-                               ionic_elliptic_info* info, hipStream_t st) {
-  ionic::CgParams c;
-  c.nx = g->nx;
-  c.ny = g->ny;
-  c.nz = g->nz;
+static ionic::CgParams cg_params_of(const ionic_bidomain_grid* g, double rtol) {
+  ionic::CgParams c = ionic::cg_params(g->nx, g->ny, g->nz);
   for (int a = 0; a < 3; ++a) {
     c.si[a] = g->sigma_i[a];
     c.sie[a] = g->sigma_i[a] + g->sigma_e[a];
   }
-  const long long n = s->n, parts = ionic::cg_blocks(c.nx, c.ny, c.nz);
-  if (work_bytes < ionic::CgWork::bytes(n, parts, max_iter))
+  c.rtol = rtol;
+  return c;
+}
+
+// One elliptic solve on stream st (synchronises it); info accumulates.  The
+// device decides convergence after every iteration (iterations after it are
+// launched but do nothing); the host reads that decision after the start and
+// after every batch of iterations: a first batch of expect - 4 when the caller
+// expects about `expect` iterations (the previous solve of a time loop), then
+// batches of 8.
+static int elliptic_solve_impl(ionic_sim* s, const ionic_bidomain_grid* g, double* u,
+                               void* work, size_t work_bytes, double rtol, int max_iter,
+                               ionic_elliptic_info* info, hipStream_t st, long long expect = 0) {
+  const ionic::CgParams c = cg_params_of(g, rtol);
+  const long long n = s->n;
+  if (work_bytes < ionic::CgWork::bytes(n, c.nb, max_iter))
     return fail(IONIC_EINVAL, "elliptic work buffer too small: need " +
-                                  std::to_string(ionic::CgWork::bytes(n, parts, max_iter)) +
+                                  std::to_string(ionic::CgWork::bytes(n, c.nb, max_iter)) +
                                   " bytes");
   double* base = static_cast<double*>(work);
   ionic::CgWork w;
   w.r = base;
   w.z = w.r + n;
-  w.p = w.z + n;
-  w.q = w.p + n;
+  w.p[0] = w.z + n;
+  w.p[1] = w.p[0] + n;
+  w.q = w.p[1] + n;
   w.part_a = w.q + n;
-  w.part_b = w.part_a + parts;
-  w.part_c = w.part_b + parts;
-  w.sc = w.part_c + parts;
-  w.n_parts = parts;
+  w.part_b = w.part_a + c.nb;
+  w.part_c = w.part_b + c.nb;
+  w.sc = w.part_c + c.nb;
   const double* V = static_cast<const double*>(s->state);
   IONIC_HIP(ionic::cg_start(c, V, u, w, st));
-  double h0[3];  // b.b, r.r at the start
-  IONIC_HIP(hipMemcpyAsync(&h0[0], w.bb(), sizeof(double), hipMemcpyDeviceToHost, st));
-  IONIC_HIP(hipMemcpyAsync(&h0[1], w.rr(0), sizeof(double), hipMemcpyDeviceToHost, st));
+  ionic::CgCtl ctl{};
+  IONIC_HIP(hipMemcpyAsync(&ctl, w.ctl(), sizeof(ctl), hipMemcpyDeviceToHost, st));
   IONIC_HIP(hipStreamSynchronize(st));
-  const double bb = h0[0];
-  double rel = bb > 0.0 ? std::sqrt(h0[1] / bb) : 0.0;
+  constexpr int kBatch = 8;
+  long long batch = std::max<long long>(kBatch, expect - 4);
   int k = 0;
-  constexpr int kCheckEvery = 4;
-  if (bb > 0.0) {
-    while (rel > rtol && k < max_iter) {
-      const int until = std::min(max_iter, k + kCheckEvery);
-      for (; k < until; ++k) IONIC_HIP(ionic::cg_iteration(c, k, u, w, st));
-      double rr = 0.0;
-      IONIC_HIP(hipMemcpyAsync(&rr, w.rr(k), sizeof(double), hipMemcpyDeviceToHost, st));
-      IONIC_HIP(hipStreamSynchronize(st));
-      rel = std::sqrt(rr / bb);
-      if (!std::isfinite(rel)) break;
-    }
-  } else {
-    // b = 0 (a spatially constant V): u is a constant, zero after the mean
+  while (!ctl.done && k < max_iter) {
+    const int until = int(std::min<long long>(max_iter, k + batch));
+    batch = kBatch;
+    for (; k < until; ++k) IONIC_HIP(ionic::cg_iteration(c, k, u, w, st));
+    if (k == max_iter) IONIC_HIP(ionic::cg_end(c, k, w, st));
+    IONIC_HIP(hipMemcpyAsync(&ctl, w.ctl(), sizeof(ctl), hipMemcpyDeviceToHost, st));
+    IONIC_HIP(hipStreamSynchronize(st));
   }
+  const long long iters = ctl.done ? ctl.iters : k;
+  double h2[2];  // b.b, r.r of the last iteration
+  IONIC_HIP(hipMemcpyAsync(&h2[0], w.bb(), sizeof(double), hipMemcpyDeviceToHost, st));
+  IONIC_HIP(hipMemcpyAsync(&h2[1], w.rr(iters), sizeof(double), hipMemcpyDeviceToHost, st));
   IONIC_HIP(ionic::cg_remove_mean(c, u, w, st));
   IONIC_HIP(hipStreamSynchronize(st));
+  const double rel = h2[0] > 0.0 ? std::sqrt(h2[1] / h2[0]) : 0.0;
   if (info) {
-    info->cg_iterations += k;
+    info->cg_iterations += iters;
     info->relative_residual = rel;
-    info->converged = info->converged && (bb == 0.0 || rel <= rtol) ? 1 : 0;
+    info->converged = info->converged && rel <= rtol ? 1 : 0;
   }
   return IONIC_OK;
 }
@@ -524,14 +531,7 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
     return fail(IONIC_EINVAL, "explicit parabolic term unstable: dt must be <= h^2 / (2 max sigma_i) = " +
                                   std::to_string(g->h * g->h / (2.0 * smax)));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
-  ionic::CgParams c;
-  c.nx = g->nx;
-  c.ny = g->ny;
-  c.nz = g->nz;
-  for (int a = 0; a < 3; ++a) {
-    c.si[a] = g->sigma_i[a];
-    c.sie[a] = g->sigma_i[a] + g->sigma_e[a];
-  }
+  const ionic::CgParams c = cg_params_of(g, rtol);
   LaunchCommon lc;
   fill_quadrature(n_nodes, lc);
   lc.tol = s->tol;
@@ -540,9 +540,12 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
   const int blocks = int((s->n + kBlock - 1) / kBlock);
   const ionic::SdcLaunch launch = s->ops->sdc[s->precision][s->predictor];
   ionic_elliptic_info acc{0, 0.0, 1, 0};
+  long long expect = 0;
   for (int k = 0; k < n_steps; ++k) {
-    rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &acc, st);
+    const long long before = acc.cg_iterations;
+    rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &acc, st, expect);
     if (rc != IONIC_OK) return rc;
+    expect = acc.cg_iterations - before;
     IONIC_HIP(ionic::bidomain_current(c, static_cast<const double*>(s->state), u_dev, g->h,
                                       i_diff_work_dev, st));
     lc.sims[0] = desc_of(s, t0, dt, i_stim_dev, stim_t_on, stim_t_off, i_diff_work_dev, k, 1,

@@ -11,6 +11,11 @@
 // the lumped mass of the node is h^d prod_a c_a / 2, where d counts the
 // directions with more than one node (the others drop out).  Everything here
 // omits the common factor h^(d-2) of the entries and h^d of the mass.
+//
+// A missing neighbour (a boundary node, or a direction with one node) gets
+// S = W = 0 for its offset and its load is redirected to an existing node, so
+// the row is evaluated without branches; a direction with one node has
+// W = (0, 1, 0) and S = 0.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,79 +23,137 @@
 namespace ionic {
 
 struct Q1Dir {
-  bool on;       // the direction has more than one node
-  int c;         // adjacent elements along it
-  double S[3], W[3];
+  double S[3], W[3];  // factors of the offsets -1, 0, +1
+  double m;           // lumped-mass factor c/2 (1 for a direction with one node)
+  long long lo, hi;   // index offsets of the -1 / +1 neighbours (0 where missing)
 };
 
-__device__ __forceinline__ Q1Dir q1_dir(long long i, long long n) {
+__device__ __forceinline__ Q1Dir q1_dir(long long i, long long n, long long stride) {
   Q1Dir d;
-  d.on = n > 1;
-  d.c = d.on ? int(i > 0) + int(i < n - 1) : 0;
-  d.S[0] = d.S[2] = -1.0;
-  d.W[0] = d.W[2] = 1.0 / 6.0;
-  d.S[1] = double(d.c);
-  d.W[1] = d.c / 3.0;
+  const bool on = n > 1, has_lo = on && i > 0, has_hi = on && i < n - 1;
+  const double c = double(int(has_lo) + int(has_hi));
+  d.S[0] = has_lo ? -1.0 : 0.0;
+  d.S[1] = c;
+  d.S[2] = has_hi ? -1.0 : 0.0;
+  d.W[0] = has_lo ? 1.0 / 6.0 : 0.0;
+  d.W[1] = on ? c / 3.0 : 1.0;
+  d.W[2] = has_hi ? 1.0 / 6.0 : 0.0;
+  d.m = on ? 0.5 * c : 1.0;
+  d.lo = has_lo ? -stride : 0;
+  d.hi = has_hi ? stride : 0;
   return d;
 }
 
 // node (i, j, k) of an nx x ny x nz grid, vertex index i + nx (j + ny k)
 struct Q1Node {
-  long long i, j, k, nx, ny, nz;
+  long long n0;
   Q1Dir dx, dy, dz;
-  __device__ __forceinline__ Q1Node(long long i_, long long j_, long long k_, long long nx_,
-                                    long long ny_, long long nz_)
-      : i(i_), j(j_), k(k_), nx(nx_), ny(ny_), nz(nz_), dx(q1_dir(i_, nx_)), dy(q1_dir(j_, ny_)),
-        dz(q1_dir(k_, nz_)) {}
+  __device__ __forceinline__ Q1Node(long long i, long long j, long long k, long long nx,
+                                    long long ny, long long nz)
+      : n0(i + nx * (j + ny * k)), dx(q1_dir(i, nx, 1)), dy(q1_dir(j, ny, nx)),
+        dz(q1_dir(k, nz, nx * ny)) {}
 
-  __device__ __forceinline__ long long index() const { return i + nx * (j + ny * k); }
+  __device__ __forceinline__ long long index() const { return n0; }
 
   // lumped mass / h^d
-  __device__ __forceinline__ double mass() const {
-    double m = 1.0;
-    if (dx.on) m *= 0.5 * dx.c;
-    if (dy.on) m *= 0.5 * dy.c;
-    if (dz.on) m *= 0.5 * dz.c;
-    return m;
-  }
-
-  __device__ __forceinline__ double coef(int ox, int oy, int oz, const double (&s)[3]) const {
-    const double Wx = dx.on ? dx.W[ox + 1] : 1.0, Wy = dy.on ? dy.W[oy + 1] : 1.0,
-                 Wz = dz.on ? dz.W[oz + 1] : 1.0;
-    double c = 0.0;
-    if (dx.on) c += s[0] * dx.S[ox + 1] * Wy * Wz;
-    if (dy.on) c += s[1] * dy.S[oy + 1] * Wx * Wz;
-    if (dz.on) c += s[2] * dz.S[oz + 1] * Wx * Wy;
-    return c;
-  }
+  __device__ __forceinline__ double mass() const { return dx.m * dy.m * dz.m; }
 
   // diagonal entry / h^(d-2)
-  __device__ __forceinline__ double diag(const double (&s)[3]) const { return coef(0, 0, 0, s); }
+  __device__ __forceinline__ double diag(const double (&s)[3]) const {
+    return s[0] * dx.S[1] * dy.W[1] * dz.W[1] + s[1] * dx.W[1] * dy.S[1] * dz.W[1] +
+           s[2] * dx.W[1] * dy.W[1] * dz.S[1];
+  }
 
-  // (A_s x)_node / h^(d-2).  Every row sums to zero (constants are in the null
-  // space), so the row is applied to differences from the node's own value,
-  // sum_{o != 0} a_o (x_{node+o} - x_node): a field with a large common offset
-  // (V near -85 mV) loses nothing to cancellation, and a constant field gives
-  // exactly zero.  The entries a_o of a pair of nodes are the same products in
-  // both rows, so the operator stays exactly symmetric.
+  // (A_s x)_node / h^(d-2), x given by val(index).  Every row sums to zero
+  // (constants are in the null space), so the row is applied to differences
+  // from the node's own value, sum_o a_o (x_{node+o} - x_node): a field with a
+  // large common offset (V near -85 mV) loses nothing to cancellation, and a
+  // constant field gives exactly zero.  The 27 entries are products of one
+  // factor per direction, so the sum is taken direction by direction: along x
+  // within each of the 9 rows, then along y, then along z (about 120 flops
+  // instead of forming 26 entries).
+  template <class Val>
+  __device__ __forceinline__ double apply_with(Val val, const double (&s)[3]) const {
+    const double xc = val(n0);
+    const long long ox[3] = {dx.lo, 0, dx.hi}, oy[3] = {dy.lo, 0, dy.hi},
+                    oz[3] = {dz.lo, 0, dz.hi};
+    double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double ww = 0.0, ws = 0.0, sw = 0.0;  // sum_y W_y (sum_x W_x d), W_y (S_x d), S_y (W_x d)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const long long row = n0 + oz[c] + oy[b];
+        double xw = 0.0, xs = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const double d = val(row + ox[a]) - xc;
+          xw += dx.W[a] * d;
+          xs += dx.S[a] * d;
+        }
+        ww += dy.W[b] * xw;
+        ws += dy.W[b] * xs;
+        sw += dy.S[b] * xw;
+      }
+      ax += dz.W[c] * ws;
+      ay += dz.W[c] * sw;
+      az += dz.S[c] * ww;
+    }
+    return s[0] * ax + s[1] * ay + s[2] * az;
+  }
+
   __device__ __forceinline__ double apply(const double* __restrict__ x,
                                           const double (&s)[3]) const {
-    const double xc = x[index()];
-    double acc = 0.0;
-    for (int oz = -1; oz <= 1; ++oz) {
-      if ((!dz.on && oz != 0) || k + oz < 0 || k + oz >= nz) continue;
-      for (int oy = -1; oy <= 1; ++oy) {
-        if ((!dy.on && oy != 0) || j + oy < 0 || j + oy >= ny) continue;
-        const double* row = x + nx * ((j + oy) + ny * (k + oz));
-        for (int ox = -1; ox <= 1; ++ox) {
-          if ((!dx.on && ox != 0) || i + ox < 0 || i + ox >= nx) continue;
-          if (ox == 0 && oy == 0 && oz == 0) continue;
-          acc += coef(ox, oy, oz, s) * (row[i + ox] - xc);
+    return apply_with([x](long long t) { return x[t]; }, s);
+  }
+
+  // The same row when the lanes of the wavefront hold consecutive nodes: each
+  // lane loads only its own column of the 9 rows (offsets in y and z), and the
+  // -1 / +1 neighbours along x come from the previous / next lane.  Where a
+  // node has an x-neighbour it is the adjacent node of the same x-row, so the
+  // adjacent lane used the same y and z offsets; where it has none, the weight
+  // is zero.  Every lane of the wavefront must call this together; lanes 0 and
+  // 63 only supply values (their own results lack a neighbour).  x is given by
+  // val(index); xc receives this lane's own value.
+  template <class Val>
+  __device__ __forceinline__ double apply_lanes(Val val, const double (&s)[3], double& xc) const {
+    xc = val(n0);
+    const long long oy[3] = {dy.lo, 0, dy.hi}, oz[3] = {dz.lo, 0, dz.hi};
+    double ax = 0.0, ay = 0.0, az = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      double ww = 0.0, ws = 0.0, sw = 0.0;
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double xm = val(n0 + oz[c] + oy[b]);
+        const double d[3] = {__shfl_up(xm, 1, 64) - xc, xm - xc, __shfl_down(xm, 1, 64) - xc};
+        double xw = 0.0, xs = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          xw += dx.W[a] * d[a];
+          xs += dx.S[a] * d[a];
         }
+        ww += dy.W[b] * xw;
+        ws += dy.W[b] * xs;
+        sw += dy.S[b] * xw;
       }
+      ax += dz.W[c] * ws;
+      ay += dz.W[c] * sw;
+      az += dz.S[c] * ww;
     }
-    return acc;
+    return s[0] * ax + s[1] * ay + s[2] * az;
   }
 };
+
+// (i, j, k) of vertex v of an nx x ny x nz grid with fewer than 2^31 nodes
+// (32-bit division)
+struct Q1Coords {
+  long long i, j, k;
+};
+__device__ __forceinline__ Q1Coords q1_coords(long long v, long long nx, long long ny) {
+  const unsigned int uv = unsigned(v), unx = unsigned(nx), uny = unsigned(ny);
+  const unsigned int jk = uv / unx;
+  return {(long long)(uv - jk * unx), (long long)(jk % uny), (long long)(jk / uny)};
+}
 
 }  // namespace ionic
