@@ -49,10 +49,15 @@ STATE_BYTES = {"fp64": 19 * 8 * 1_000_000, "mixed": (6 * 8 + 13 * 4) * 1_000_000
 
 
 def kernel_source_hash():
-    """Hash of the kernel sources and build flags the traffic counters belong to."""
+    """Hash of the sources and build flags of the step kernels, which the traffic
+    counters belong to: the step translation units (kernels_*.hip) and the
+    headers they include; the stencil, elliptic and control sources are not
+    part of those kernels."""
     h = hashlib.sha1()
     for fn in sorted(os.listdir(CSRC)):
-        if fn.endswith((".h", ".hip")):
+        if (fn.startswith("kernels_") and fn.endswith(".hip")) or fn in (
+                "sdc_kernel.h", "dual.h", "sparse_solve.h", "kernel_ops.h", "kernel_ops_impl.h",
+                "model_lr91.h", "model_tt06.h", "model_test.h"):
             h.update(fn.encode())
             with open(os.path.join(CSRC, fn), "rb") as f:
                 h.update(f.read())

@@ -10,7 +10,7 @@
 // the first state plane (double in every precision layout), read through the
 // L1/L2 caches for the neighbours.  The kernel moves 16 bytes per node from HBM
 // (V once, I_diff once).  Grids have fewer than 2^31 nodes.
-#include "kernel_ops.h"
+#include "grid_ops.h"
 #include "stencil.h"
 
 namespace ionic {

@@ -33,7 +33,7 @@
 // slots of iteration k-1 and tests ||r_k|| <= rtol ||b||: done is set there,
 // after which every queued launch returns at once; the host only reads the
 // flag between batches of launches.
-#include "kernel_ops.h"
+#include "grid_ops.h"
 #include "stencil.h"
 
 namespace ionic {
@@ -285,6 +285,15 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 __global__ void __launch_bounds__(kThreads)
+    extrapolate_kernel(CgParams c, double* __restrict__ U, double* __restrict__ u_prev, int first) {
+  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
+    const double u = U[v];
+    if (!first) U[v] = 2.0 * u - u_prev[v];
+    u_prev[v] = u;
+  }
+}
+
+__global__ void __launch_bounds__(kThreads)
     bidomain_current_kernel(const double* __restrict__ V, const double* __restrict__ U, CgParams c,
                             double inv_h2, double* __restrict__ out) {
   for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
@@ -332,6 +341,12 @@ hipError_t cg_remove_mean(const CgParams& c, double* U, CgWork& w, hipStream_t s
   const dim3 g(unsigned(c.nb)), b(kThreads);
   hipLaunchKernelGGL(mean_parts_kernel, g, b, 0, st, U, c, w);
   hipLaunchKernelGGL(sub_mean_kernel, g, b, 0, st, c, w, U);
+  return hipGetLastError();
+}
+
+hipError_t cg_extrapolate(const CgParams& c, double* U, CgWork& w, bool first, hipStream_t st) {
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, c, U,
+                     w.u_prev, first ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -11,6 +11,7 @@
 #include <string>
 #include <vector>
 
+#include "grid_ops.h"
 #include "ionic_sdc.h"
 #include "kernel_ops.h"
 
@@ -423,7 +424,7 @@ static int check_bidomain_grid(const ionic_sim* s, const ionic_bidomain_grid* g)
   return IONIC_OK;
 }
 
-// One elliptic solve on stream st (synchronises it); info accumulates.
+// CG parameters of a bidomain grid.
 static ionic::CgParams cg_params_of(const ionic_bidomain_grid* g, double rtol) {
   ionic::CgParams c = ionic::cg_params(g->nx, g->ny, g->nz);
   for (int a = 0; a < 3; ++a) {
@@ -432,6 +433,23 @@ static ionic::CgParams cg_params_of(const ionic_bidomain_grid* g, double rtol) {
   }
   c.rtol = rtol;
   return c;
+}
+
+// The vectors and scalars of a solve in the caller's work buffer.
+static ionic::CgWork carve_cg_work(void* work, long long n, long long nb) {
+  double* base = static_cast<double*>(work);
+  ionic::CgWork w;
+  w.r = base;
+  w.z = w.r + n;
+  w.p[0] = w.z + n;
+  w.p[1] = w.p[0] + n;
+  w.q = w.p[1] + n;
+  w.u_prev = w.q + n;
+  w.part_a = w.u_prev + n;
+  w.part_b = w.part_a + nb;
+  w.part_c = w.part_b + nb;
+  w.sc = w.part_c + nb;
+  return w;
 }
 
 // One elliptic solve on stream st (synchronises it); info accumulates.  The
@@ -449,17 +467,7 @@ static int elliptic_solve_impl(ionic_sim* s, const ionic_bidomain_grid* g, doubl
     return fail(IONIC_EINVAL, "elliptic work buffer too small: need " +
                                   std::to_string(ionic::CgWork::bytes(n, c.nb, max_iter)) +
                                   " bytes");
-  double* base = static_cast<double*>(work);
-  ionic::CgWork w;
-  w.r = base;
-  w.z = w.r + n;
-  w.p[0] = w.z + n;
-  w.p[1] = w.p[0] + n;
-  w.q = w.p[1] + n;
-  w.part_a = w.q + n;
-  w.part_b = w.part_a + c.nb;
-  w.part_c = w.part_b + c.nb;
-  w.sc = w.part_c + c.nb;
+  ionic::CgWork w = carve_cg_work(work, n, c.nb);
   const double* V = static_cast<const double*>(s->state);
   IONIC_HIP(ionic::cg_start(c, V, u, w, st));
   ionic::CgCtl ctl{};
@@ -541,7 +549,11 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
   const ionic::SdcLaunch launch = s->ops->sdc[s->precision][s->predictor];
   ionic_elliptic_info acc{0, 0.0, 1, 0};
   long long expect = 0;
+  ionic::CgWork w = carve_cg_work(work_dev, s->n, c.nb);
   for (int k = 0; k < n_steps; ++k) {
+    // the guess: the caller's u, then the last solution, then linear
+    // extrapolation from the last two
+    if (k >= 1) IONIC_HIP(ionic::cg_extrapolate(c, u_dev, w, k == 1, st));
     const long long before = acc.cg_iterations;
     rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &acc, st, expect);
     if (rc != IONIC_OK) return rc;

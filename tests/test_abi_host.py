@@ -148,12 +148,12 @@ def test_diffusion_entry_points_reject_bad_arguments():
 
 
 def test_elliptic_work_bytes_and_rejections():
-    # 5 vectors, one partial sum per block for 3 quantities (at most 1024 blocks of 256
+    # 6 vectors, one partial sum per block for 3 quantities (at most 1024 blocks of 256
     # threads, a multiple of 8), 8 scalars, 3 per iteration
     n, parts = 100 * 100 * 100, 1024
-    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (5 * n + 3 * parts + 8 + 3 * 52)
-    assert I.ionic_elliptic_work_bytes(40, 1, 1, 10) == 8 * (5 * 40 + 3 * 8 + 8 + 3 * 12)
-    assert I.ionic_elliptic_work_bytes(300, 256, 1, 10) == 8 * (5 * 76800 + 3 * 304 + 8 + 3 * 12)
+    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (6 * n + 3 * parts + 8 + 3 * 52)
+    assert I.ionic_elliptic_work_bytes(40, 1, 1, 10) == 8 * (6 * 40 + 3 * 8 + 8 + 3 * 12)
+    assert I.ionic_elliptic_work_bytes(300, 256, 1, 10) == 8 * (6 * 76800 + 3 * 304 + 8 + 3 * 12)
     assert I.ionic_elliptic_work_bytes(2 ** 16, 2 ** 15, 1, 10) == 0     # 2^31 nodes
     assert I.ionic_elliptic_work_bytes(0, 1, 1, 10) == 0
     assert I.ionic_elliptic_work_bytes(10, 1, 1, -1) == 0
