@@ -288,12 +288,16 @@ size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_ite
  * the current V field, A_i and A_ie the Q1 stiffness matrices of sigma_i and
  * sigma_i + sigma_e, homogeneous Neumann boundaries.  u_dev (N doubles,
  * device) holds the initial guess and receives the solution, whose
- * lumped-mass mean is set to zero.  Conjugate gradients with the Jacobi
- * preconditioner until ||b - A_ie u|| <= rtol ||b|| or max_iter iterations
+ * lumped-mass mean is set to zero.  Conjugate gradients preconditioned by one
+ * geometric multigrid V-cycle on the grid's tensor-product hierarchy (Jacobi
+ * for grids of at most 512 nodes) until ||b - A_ie u|| <= rtol ||b|| or
+ * max_iter iterations
  * (not an error: info->converged = 0); info->cg_iterations is the first
  * iteration count that meets rtol (the test runs on the device after every
  * iteration).  Reductions in a fixed order, so the result is reproducible bit
  * for bit.  The paper uses BiCGSTAB with algebraic multigrid for this system.
+ * The host forms the exact inverse of the coarsest level once per grid and
+ * conductivities (kept in the handle).
  * work_dev: ionic_elliptic_work_bytes(...) bytes, not shared with a solve
  * running at the same time.  Synchronises hip_stream (the host reads the
  * device's convergence flag between batches of iteration launches). */

@@ -10,8 +10,8 @@
 // (Neumann boundaries) and -A_i v sums to zero, so conjugate gradients
 // converge on it; the lumped-mass mean of u is then set to zero.  The paper
 // solves this system with BiCGSTAB and algebraic multigrid; here it is
-// conjugate gradients with the Jacobi preconditioner, warm-started from the
-// previous step's u.
+// conjugate gradients, preconditioned by the geometric multigrid cycle of
+// multigrid.hip (or by Jacobi on grids too small for a hierarchy).
 //
 // Launch shape: nb blocks of 256 threads (nb a multiple of 8, at most 1024);
 // block L owns the nodes [L chunk, (L + 1) chunk), its threads stride through
@@ -28,8 +28,9 @@
 // kernels that consume a total also record it (block 0) in the scalars of
 // iteration k (rz[k], pq[k], rr[k]).
 //
-// An iteration is two launches: cg_q_kernel (direction and q = A_ie p) and
-// cg_update_kernel (u, r, z).  The first launch of iteration k adds the r.r
+// An iteration is two launches, cg_q_kernel (direction and q = A_ie p) and
+// cg_update_kernel (u, r; z with Jacobi), then the multigrid cycle for z.
+// The first launch of iteration k (the cycle's, with multigrid) adds the r.r
 // slots of iteration k-1 and tests ||r_k|| <= rtol ||b||: done is set there,
 // after which every queued launch returns at once; the host only reads the
 // flag between batches of launches.
@@ -119,38 +120,54 @@ __device__ __forceinline__ Nodes my_nodes(const CgParams& c) {
   return {begin + threadIdx.x, end < c.n ? end : c.n};
 }
 
+// r = b - A_ie U with b = -A_i V; with the Jacobi preconditioner also z = r /
+// diag (the multigrid cycle forms z otherwise); block parts of b.b (part_a),
+// r.z (part_b, Jacobi only) and r.r (part_c)
 __global__ void __launch_bounds__(kThreads)
     cg_start_kernel(const double* __restrict__ V, const double* __restrict__ U, CgParams c,
-                    CgWork w) {
-  double s[3] = {0.0, 0.0, 0.0};  // r.z, b.b, r.r
+                    CgWork w, int jacobi) {
+  // a new solve: clear the previous solve's stop flag before any launch that
+  // tests it (no kernel of this launch reads it)
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    w.ctl()->done = 0;
+    w.ctl()->iters = 0;
+  }
+  double s[3] = {0.0, 0.0, 0.0};  // b.b, r.z, r.r
   for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
     const Q1Coords x = q1_coords(v, c.nx, c.ny);
     const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
     const double b = -node.apply(V, c.si);
     const double rn = b - node.apply(U, c.sie);
-    const double zn = rn / node.diag(c.sie);
     w.r[v] = rn;
-    w.z[v] = zn;
-    w.p_k(-1)[v] = 0.0;  // p_0 = z_0
-    s[0] += rn * zn;
-    s[1] += b * b;
+    if (jacobi) {
+      const double zn = rn / node.diag(c.sie);
+      w.z[v] = zn;
+      s[1] += rn * zn;
+    }
+    s[0] += b * b;
     s[2] += rn * rn;
   }
-  double* const part[3] = {w.part_a, w.part_b, w.part_c};
-  put_partials(s, part, c);
+  if (jacobi) {
+    double* const part[3] = {w.part_a, w.part_b, w.part_c};
+    put_partials(s, part, c);
+  } else {
+    double t[2] = {s[0], s[2]};
+    double* const part[2] = {w.part_a, w.part_c};
+    put_partials(t, part, c);
+  }
 }
 
 // one block: the scalars of the start and the test before the first iteration
 __global__ void __launch_bounds__(kThreads) cg_start_sums_kernel(CgParams c, CgWork w) {
   const double* const part[3] = {w.part_a, w.part_b, w.part_c};
-  double s[3];
+  double s[3];  // b.b, r.z, r.r
   total_of(part, c, s);
   if (threadIdx.x == 0) {
-    *w.rz(0) = s[0];
-    *w.bb() = s[1];
+    *w.bb() = s[0];
+    *w.rz(0) = s[1];
     *w.rr(0) = s[2];
     CgCtl* ctl = w.ctl();
-    ctl->done = converged(c, s[2], s[1]) ? 1 : 0;
+    ctl->done = converged(c, s[2], s[0]) ? 1 : 0;
     ctl->reserved = 0;
     ctl->iters = 0;
   }
@@ -190,7 +207,9 @@ __global__ void __launch_bounds__(kThreads) cg_q_kernel(CgParams c, CgWork w, lo
   const double* __restrict__ z = w.z;
   const double* __restrict__ p_old = w.p_k(k - 1);
   double* __restrict__ p_new = w.p_k(k);
-  const auto p_of = [=](long long t) { return z[t] + beta * p_old[t]; };
+  // p_0 = z_0 (p_old holds no direction yet: not read into the value)
+  const bool first = k == 0;
+  const auto p_of = [=](long long t) { return first ? z[t] : z[t] + beta * p_old[t]; };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long begin = chunk_id(c) * c.chunk;
   const long long end = begin + c.chunk < c.n ? begin + c.chunk : c.n;
@@ -213,8 +232,10 @@ __global__ void __launch_bounds__(kThreads) cg_q_kernel(CgParams c, CgWork w, lo
   put_partials(s, part, c);
 }
 
+// u += alpha p, r -= alpha q and the block's part of r.r (part_c); with the
+// Jacobi preconditioner also z = r / diag and the part of r.z (part_b)
 __global__ void __launch_bounds__(kThreads)
-    cg_update_kernel(CgParams c, CgWork w, long long k, double* __restrict__ U) {
+    cg_update_kernel(CgParams c, CgWork w, long long k, double* __restrict__ U, int jacobi) {
   if (w.ctl()->done) return;
   const double* const in[1] = {w.part_a};
   double pq[1];
@@ -224,18 +245,26 @@ __global__ void __launch_bounds__(kThreads)
   const double* __restrict__ p = w.p_k(k);
   double s[2] = {0.0, 0.0};  // r.z, r.r
   for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
-    const Q1Coords x = q1_coords(v, c.nx, c.ny);
-    const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
     U[v] += alpha * p[v];
     const double rn = w.r[v] - alpha * w.q[v];
-    const double zn = rn / node.diag(c.sie);
     w.r[v] = rn;
-    w.z[v] = zn;
-    s[0] += rn * zn;
     s[1] += rn * rn;
+    if (jacobi) {
+      const Q1Coords x = q1_coords(v, c.nx, c.ny);
+      const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
+      const double zn = rn / node.diag(c.sie);
+      w.z[v] = zn;
+      s[0] += rn * zn;
+    }
   }
-  double* const part[2] = {w.part_b, w.part_c};
-  put_partials(s, part, c);
+  if (jacobi) {
+    double* const part[2] = {w.part_b, w.part_c};
+    put_partials(s, part, c);
+  } else {
+    double t[1] = {s[1]};
+    double* const part[1] = {w.part_c};
+    put_partials(t, part, c);
+  }
 }
 
 // one block, after the last iteration launch k_end when the solve has not
@@ -317,17 +346,23 @@ CgParams cg_params(long long nx, long long ny, long long nz) {
   return c;
 }
 
-hipError_t cg_start(const CgParams& c, const double* V, const double* U, CgWork& w,
+hipError_t cg_start(const CgParams& c, const double* V, const double* U, CgWork& w, bool jacobi,
                     hipStream_t st) {
-  hipLaunchKernelGGL(cg_start_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, V, U, c, w);
+  hipLaunchKernelGGL(cg_start_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, V, U, c, w,
+                     jacobi ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t cg_start_sums(const CgParams& c, CgWork& w, hipStream_t st) {
   hipLaunchKernelGGL(cg_start_sums_kernel, dim3(1), dim3(kThreads), 0, st, c, w);
   return hipGetLastError();
 }
 
-hipError_t cg_iteration(const CgParams& c, int k, double* U, CgWork& w, hipStream_t st) {
+hipError_t cg_iteration(const CgParams& c, int k, double* U, CgWork& w, bool jacobi,
+                        hipStream_t st) {
   const dim3 g(unsigned(c.nb)), b(kThreads);
   hipLaunchKernelGGL(cg_q_kernel, g, b, 0, st, c, w, (long long)k);
-  hipLaunchKernelGGL(cg_update_kernel, g, b, 0, st, c, w, (long long)k, U);
+  hipLaunchKernelGGL(cg_update_kernel, g, b, 0, st, c, w, (long long)k, U, jacobi ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 namespace ionic {
 
@@ -13,9 +14,9 @@ namespace ionic {
 hipError_t diffusion_launch(const double* V, long long nx, long long ny, long long nz, double h,
                             double sigma, double* out, hipStream_t st);
 
-// Elliptic equation A_ie u = -A_i v by Jacobi-preconditioned conjugate
-// gradients and the current -M_L^{-1} A_i (v + u) (elliptic.hip).  Grids have
-// fewer than 2^31 nodes.
+// Elliptic equation A_ie u = -A_i v by preconditioned conjugate gradients
+// and the current -M_L^{-1} A_i (v + u) (elliptic.hip).  Grids have fewer
+// than 2^31 nodes.
 struct CgParams {
   long long nx, ny, nz;
   long long n;      // nx ny nz
@@ -57,16 +58,66 @@ struct CgWork {
   }
 };
 static_assert(sizeof(CgCtl) == 2 * sizeof(double), "CgCtl occupies scalars 3 and 4");
-// r, z, p from the guess U and the field V; r.z, b.b, r.r; done if already converged
-hipError_t cg_start(const CgParams& c, const double* V, const double* U, CgWork& w,
+// r (and with jacobi z) from the guess U and the field V, and the block parts
+// of b.b, r.z (jacobi) and r.r; cg_start_sums then forms the scalars of
+// iteration 0 (with the multigrid preconditioner after z and its r.z parts
+// come from mg_apply) and tests convergence
+hipError_t cg_start(const CgParams& c, const double* V, const double* U, CgWork& w, bool jacobi,
                     hipStream_t st);
+hipError_t cg_start_sums(const CgParams& c, CgWork& w, hipStream_t st);
 // iteration k (k = 0, 1, ...): no work once done; the test of ||r_k|| runs at
-// the start of iteration k
-hipError_t cg_iteration(const CgParams& c, int k, double* U, CgWork& w, hipStream_t st);
+// the start of iteration k; without jacobi, z and its r.z parts must come from
+// mg_apply after each iteration
+hipError_t cg_iteration(const CgParams& c, int k, double* U, CgWork& w, bool jacobi,
+                        hipStream_t st);
 // after the last iteration launch (k_end launched iterations): the scalars and
 // the test of ||r_(k_end)|| if the solve has not stopped
 hipError_t cg_end(const CgParams& c, int k_end, CgWork& w, hipStream_t st);
 hipError_t cg_remove_mean(const CgParams& c, double* U, CgWork& w, hipStream_t st);
+// Geometric multigrid preconditioner (multigrid.hip): one symmetric V(1,1)
+// cycle on the tensor-product hierarchy of the grid.
+constexpr int kMgMaxLevels = 16;
+struct MgLevel {
+  long long nx, ny, nz, n;
+  long long nb, chunk;       // launch shape, as CgParams
+  double s[3];               // sigma_i + sigma_e per direction
+  const double* K[3];        // 1D stiffness rows, 3 per index (offsets -1, 0, +1)
+  const double* M[3];        // 1D mass rows
+  const double* I0[3];       // prolongation from the next level: fine index i
+  const double* w0[3];       //   takes w0 x_c[I0] + w1 x_c[I0 + 1]
+  const double* w1[3];
+  int coarsened[3];          // the next level halves this direction
+  double *invd, *x, *y, *b;  // n each (x, y, b on levels >= 1 only)
+};
+struct MgLevels {
+  int count;
+  MgLevel lv[kMgMaxLevels];
+  const double* coarse_inverse;  // dense inverse of the coarsest level (row-major)
+};
+struct MgPlan {
+  int levels;
+  bool usable;  // at least two levels and a coarsest level of at most 512 nodes
+  long long dims[kMgMaxLevels][3];
+  size_t off_K[kMgMaxLevels][3], off_M[kMgMaxLevels][3], off_P[kMgMaxLevels][3];
+  size_t off_inv;  // the coarsest level's dense inverse
+  size_t table_doubles, vector_doubles;
+};
+MgPlan mg_plan(long long nx, long long ny, long long nz);
+size_t mg_doubles(const MgPlan& p);  // device doubles of tables and vectors (0 if unusable)
+std::vector<double> mg_tables(const MgPlan& p);
+// fills the coarsest inverse of tables for the conductivities s
+void mg_coarse_inverse(const MgPlan& p, const double s[3], std::vector<double>& tables);
+MgLevels mg_bind(const MgPlan& p, const double sie[3], double* region);
+hipError_t mg_setup(const MgLevels& L, hipStream_t st);
+// z = cycle(r), and the block parts of r.z into rz_part (the CG's layout);
+// xtmp, ytmp: n doubles each, free for the call.  With iter >= 0 the first
+// launch first tests ||r_iter|| from the r.r parts (rr_part, n_parts) and
+// stops the solve (ctl) if it meets rtol, recording r.r at rr_out.
+hipError_t mg_apply(const MgLevels& L, const double* r, double* z, double* xtmp, double* ytmp,
+                    CgCtl* ctl, double* rz_part, const double* rr_part, long long n_parts,
+                    const double* bb, double rtol, double* rr_out, long long iter,
+                    hipStream_t st);
+
 // initial guess of a time loop's next solve: with first, u_prev = U (the guess
 // stays U); otherwise U = 2 U - u_prev and u_prev = the old U (linear
 // extrapolation from the last two solutions)

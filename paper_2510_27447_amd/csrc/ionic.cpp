@@ -141,6 +141,11 @@ struct ionic_sim {
   const double* i_stim = nullptr;
   const double* i_diff = nullptr;
   long long step_offset = 0;
+  // multigrid tables of the last bidomain grid (the coarsest inverse costs
+  // O(n^3) on the host, so it is formed once per grid and conductivities)
+  long long mg_dims[3] = {0, 0, 0};
+  double mg_sie[3] = {0.0, 0.0, 0.0};
+  std::vector<double> mg_tables;
 
   const void* params() const { return precision == IONIC_FP64 ? (const void*)p64 : (const void*)p32; }
 };
@@ -400,10 +405,18 @@ int reaction_diffusion_step(ionic_sim* s, const ionic_grid* g, double t0, double
   return IONIC_OK;
 }
 
+// Work of a solve: the CG vectors and scalars, then (when the grid has a
+// multigrid hierarchy) the level tables and vectors.
+static size_t elliptic_bytes(long long nx, long long ny, long long nz, int max_iter) {
+  const long long n = nx * ny * nz;
+  return ionic::CgWork::bytes(n, ionic::cg_params(nx, ny, nz).nb, max_iter) +
+         sizeof(double) * ionic::mg_doubles(ionic::mg_plan(nx, ny, nz));
+}
+
 size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_iter) {
   if (nx < 1 || ny < 1 || nz < 1 || max_iter < 0 || max_iter > (1 << 24)) return 0;
   if ((__int128)nx * ny * nz >= ((__int128)1 << 31)) return 0;
-  return ionic::CgWork::bytes(nx * ny * nz, ionic::cg_params(nx, ny, nz).nb, max_iter);
+  return elliptic_bytes(nx, ny, nz, max_iter);
 }
 
 static int check_bidomain_grid(const ionic_sim* s, const ionic_bidomain_grid* g) {
@@ -452,34 +465,74 @@ static ionic::CgWork carve_cg_work(void* work, long long n, long long nb) {
   return w;
 }
 
+// The preconditioner of the solves of one call: multigrid when the grid has
+// a hierarchy (its tables uploaded and its inverse diagonals formed once per
+// call; the host tables are kept in the handle), else Jacobi.
+struct Preconditioner {
+  bool mg = false;
+  ionic::MgLevels levels{};
+};
+
+static int prepare_preconditioner(ionic_sim* s, const ionic::CgParams& c, void* work,
+                                  int max_iter, Preconditioner& pc, hipStream_t st) {
+  const ionic::MgPlan plan = ionic::mg_plan(c.nx, c.ny, c.nz);
+  pc.mg = plan.usable;
+  if (!pc.mg) return IONIC_OK;
+  const bool same = s->mg_dims[0] == c.nx && s->mg_dims[1] == c.ny && s->mg_dims[2] == c.nz &&
+                    s->mg_sie[0] == c.sie[0] && s->mg_sie[1] == c.sie[1] &&
+                    s->mg_sie[2] == c.sie[2] && s->mg_tables.size() == plan.table_doubles;
+  if (!same) {
+    s->mg_tables = ionic::mg_tables(plan);
+    ionic::mg_coarse_inverse(plan, c.sie, s->mg_tables);
+    s->mg_dims[0] = c.nx;
+    s->mg_dims[1] = c.ny;
+    s->mg_dims[2] = c.nz;
+    for (int a = 0; a < 3; ++a) s->mg_sie[a] = c.sie[a];
+  }
+  double* region = static_cast<double*>(work) + ionic::CgWork::bytes(c.n, c.nb, max_iter) / sizeof(double);
+  IONIC_HIP(hipMemcpyAsync(region, s->mg_tables.data(), s->mg_tables.size() * sizeof(double),
+                           hipMemcpyHostToDevice, st));
+  pc.levels = ionic::mg_bind(plan, c.sie, region);
+  IONIC_HIP(ionic::mg_setup(pc.levels, st));
+  return IONIC_OK;
+}
+
 // One elliptic solve on stream st (synchronises it); info accumulates.  The
 // device decides convergence after every iteration (iterations after it are
 // launched but do nothing); the host reads that decision after the start and
 // after every batch of iterations: a first batch of expect - 4 when the caller
 // expects about `expect` iterations (the previous solve of a time loop), then
-// batches of 8.
-static int elliptic_solve_impl(ionic_sim* s, const ionic_bidomain_grid* g, double* u,
-                               void* work, size_t work_bytes, double rtol, int max_iter,
+// batches of 8.  work_bytes has been checked by the caller.
+static int elliptic_solve_impl(ionic_sim* s, const ionic::CgParams& c, double* u, void* work,
+                               double rtol, int max_iter, const Preconditioner& pc,
                                ionic_elliptic_info* info, hipStream_t st, long long expect = 0) {
-  const ionic::CgParams c = cg_params_of(g, rtol);
   const long long n = s->n;
-  if (work_bytes < ionic::CgWork::bytes(n, c.nb, max_iter))
-    return fail(IONIC_EINVAL, "elliptic work buffer too small: need " +
-                                  std::to_string(ionic::CgWork::bytes(n, c.nb, max_iter)) +
-                                  " bytes");
   ionic::CgWork w = carve_cg_work(work, n, c.nb);
   const double* V = static_cast<const double*>(s->state);
-  IONIC_HIP(ionic::cg_start(c, V, u, w, st));
+  const bool jacobi = !pc.mg;
+  // z = M^-1 r and its r.z parts when multigrid preconditions; with iter >= 0
+  // the cycle first tests ||r_iter|| (xtmp and ytmp are dead vectors of the CG
+  // at that point)
+  auto cycle = [&](double* ytmp, long long iter) {
+    return ionic::mg_apply(pc.levels, w.r, w.z, w.q, ytmp, w.ctl(), w.part_b, w.part_c, c.nb,
+                           w.bb(), rtol, iter >= 0 ? w.rr(iter) : nullptr, iter, st);
+  };
+  IONIC_HIP(ionic::cg_start(c, V, u, w, jacobi, st));
+  if (!jacobi) IONIC_HIP(cycle(w.p_k(0), -1));
+  IONIC_HIP(ionic::cg_start_sums(c, w, st));
   ionic::CgCtl ctl{};
   IONIC_HIP(hipMemcpyAsync(&ctl, w.ctl(), sizeof(ctl), hipMemcpyDeviceToHost, st));
   IONIC_HIP(hipStreamSynchronize(st));
   constexpr int kBatch = 8;
-  long long batch = std::max<long long>(kBatch, expect - 4);
+  long long batch = std::max<long long>(jacobi ? kBatch : 1, expect - (jacobi ? 4 : 1));
   int k = 0;
   while (!ctl.done && k < max_iter) {
     const int until = int(std::min<long long>(max_iter, k + batch));
-    batch = kBatch;
-    for (; k < until; ++k) IONIC_HIP(ionic::cg_iteration(c, k, u, w, st));
+    batch = jacobi ? kBatch : 2;
+    for (; k < until; ++k) {
+      IONIC_HIP(ionic::cg_iteration(c, k, u, w, jacobi, st));
+      if (!jacobi) IONIC_HIP(cycle(w.p_k(k + 1), k + 1));
+    }
     if (k == max_iter) IONIC_HIP(ionic::cg_end(c, k, w, st));
     IONIC_HIP(hipMemcpyAsync(&ctl, w.ctl(), sizeof(ctl), hipMemcpyDeviceToHost, st));
     IONIC_HIP(hipStreamSynchronize(st));
@@ -499,6 +552,14 @@ static int elliptic_solve_impl(ionic_sim* s, const ionic_bidomain_grid* g, doubl
   return IONIC_OK;
 }
 
+static int check_elliptic_work(const ionic::CgParams& c, size_t work_bytes, int max_iter) {
+  const size_t need = elliptic_bytes(c.nx, c.ny, c.nz, max_iter);
+  if (work_bytes < need)
+    return fail(IONIC_EINVAL, "elliptic work buffer too small: need " + std::to_string(need) +
+                                  " bytes");
+  return IONIC_OK;
+}
+
 int ionic_elliptic_solve(ionic_sim* s, const ionic_bidomain_grid* g, double* u_dev,
                          void* work_dev, size_t work_bytes, double rtol, int max_iter,
                          ionic_elliptic_info* info, void* hip_stream) {
@@ -508,9 +569,15 @@ int ionic_elliptic_solve(ionic_sim* s, const ionic_bidomain_grid* g, double* u_d
   if (!u_dev || !work_dev) return fail(IONIC_EINVAL, "u_dev or work_dev is NULL");
   if (!(rtol >= 0.0) || !std::isfinite(rtol)) return fail(IONIC_EINVAL, "rtol must be >= 0");
   if (max_iter < 0 || max_iter > (1 << 24)) return fail(IONIC_EINVAL, "max_iter out of range");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  const ionic::CgParams c = cg_params_of(g, rtol);
+  rc = check_elliptic_work(c, work_bytes, max_iter);
+  if (rc != IONIC_OK) return rc;
+  Preconditioner pc;
+  rc = prepare_preconditioner(s, c, work_dev, max_iter, pc, st);
+  if (rc != IONIC_OK) return rc;
   ionic_elliptic_info local{0, 0.0, 1, 0};
-  rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &local,
-                           static_cast<hipStream_t>(hip_stream));
+  rc = elliptic_solve_impl(s, c, u_dev, work_dev, rtol, max_iter, pc, &local, st);
   if (rc != IONIC_OK) return rc;
   if (info) *info = local;
   return IONIC_OK;
@@ -547,6 +614,11 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
   lc.n_sims = 1;
   const int blocks = int((s->n + kBlock - 1) / kBlock);
   const ionic::SdcLaunch launch = s->ops->sdc[s->precision][s->predictor];
+  rc = check_elliptic_work(c, work_bytes, max_iter);
+  if (rc != IONIC_OK) return rc;
+  Preconditioner pc;
+  rc = prepare_preconditioner(s, c, work_dev, max_iter, pc, st);
+  if (rc != IONIC_OK) return rc;
   ionic_elliptic_info acc{0, 0.0, 1, 0};
   long long expect = 0;
   ionic::CgWork w = carve_cg_work(work_dev, s->n, c.nb);
@@ -555,7 +627,7 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
     // extrapolation from the last two
     if (k >= 1) IONIC_HIP(ionic::cg_extrapolate(c, u_dev, w, k == 1, st));
     const long long before = acc.cg_iterations;
-    rc = elliptic_solve_impl(s, g, u_dev, work_dev, work_bytes, rtol, max_iter, &acc, st, expect);
+    rc = elliptic_solve_impl(s, c, u_dev, work_dev, rtol, max_iter, pc, &acc, st, expect);
     if (rc != IONIC_OK) return rc;
     expect = acc.cg_iterations - before;
     IONIC_HIP(ionic::bidomain_current(c, static_cast<const double*>(s->state), u_dev, g->h,

@@ -147,13 +147,40 @@ def test_diffusion_entry_points_reject_bad_arguments():
                                        0.0, None, None) == -1
 
 
+def _mg_doubles(shape):
+    """Device doubles of the multigrid hierarchy of a grid: levels halve every
+    extent above 2 (n -> (n+1)/2 odd, n/2+1 even) until 512 nodes or fewer; per
+    level and direction 1D stiffness and mass rows (3 per index) and, except on
+    the coarsest, the prolongation (3 per index), then the coarsest level's dense
+    inverse, padded to 32; the inverse diagonal of every level and x, y, b of
+    the coarse ones, each padded to 32.  0 without a hierarchy."""
+    def pad(k):
+        return (k + 31) // 32 * 32
+    dims = [tuple(shape)]
+    while True:
+        d = dims[-1]
+        c = tuple(n if n <= 2 else ((n + 1) // 2 if n % 2 else n // 2 + 1) for n in d)
+        if int(np.prod(d)) <= 512 or c == d or len(dims) == 16:
+            break
+        dims.append(c)
+    if len(dims) < 2 or int(np.prod(dims[-1])) > 512:
+        return 0
+    tables = sum(sum((6 + (3 if l + 1 < len(dims) else 0)) * n for n in d)
+                 for l, d in enumerate(dims)) + int(np.prod(dims[-1])) ** 2
+    vectors = sum((1 if l == 0 else 4) * pad(int(np.prod(d))) for l, d in enumerate(dims))
+    return pad(tables) + vectors
+
+
 def test_elliptic_work_bytes_and_rejections():
     # 6 vectors, one partial sum per block for 3 quantities (at most 1024 blocks of 256
-    # threads, a multiple of 8), 8 scalars, 3 per iteration
+    # threads, a multiple of 8), 8 scalars, 3 per iteration; then the multigrid levels
     n, parts = 100 * 100 * 100, 1024
-    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (6 * n + 3 * parts + 8 + 3 * 52)
+    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (6 * n + 3 * parts + 8 + 3 * 52
+                                                                  + _mg_doubles((100, 100, 100)))
+    assert _mg_doubles((40, 1, 1)) == 0 and _mg_doubles((9, 8, 5)) == 0  # Jacobi only
     assert I.ionic_elliptic_work_bytes(40, 1, 1, 10) == 8 * (6 * 40 + 3 * 8 + 8 + 3 * 12)
-    assert I.ionic_elliptic_work_bytes(300, 256, 1, 10) == 8 * (6 * 76800 + 3 * 304 + 8 + 3 * 12)
+    assert I.ionic_elliptic_work_bytes(300, 256, 1, 10) == 8 * (6 * 76800 + 3 * 304 + 8 + 3 * 12
+                                                                + _mg_doubles((300, 256, 1)))
     assert I.ionic_elliptic_work_bytes(2 ** 16, 2 ** 15, 1, 10) == 0     # 2^31 nodes
     assert I.ionic_elliptic_work_bytes(0, 1, 1, 10) == 0
     assert I.ionic_elliptic_work_bytes(10, 1, 1, -1) == 0

@@ -3,7 +3,8 @@ section 3.1, equation semi-elliptic; Algorithm 2, first box) and for
 partitioned bidomain stepping (one pass of Algorithm 2 per step), through
 the C ABI, on structured grids with diagonal conductivity tensors.
 
-Bars: u against the oracle's direct solve to 1e-9 of its scale at a CG
+Grids of at most 512 nodes use the Jacobi preconditioner, larger ones the
+multigrid cycle.  Bars: u against the oracle's direct solve to 1e-9 of its scale at a CG
 tolerance of 1e-13 (random fields); coupled runs at a CG tolerance of 1e-11; the solve reproducible bit for bit; coupled runs as the
 other parity tests (fp64 1e-10 on V, mixed 1e-4 against the fp64 oracle);
 sigma_e = sigma_i equal to monodomain stepping."""
@@ -30,7 +31,10 @@ def _buffers(shape, max_iter):
             torch.zeros(n, dtype=torch.float64, device="cuda"))
 
 
-@pytest.mark.parametrize("shape", [(9, 8, 5), (13, 11, 1), (40, 1, 1), (70, 3, 2)])
+# (9, 8, 5) ... (70, 3, 2): at most 512 nodes, Jacobi-preconditioned; (24, 20, 3)
+# and (30, 24, 10): multigrid with 2 and 3 levels
+@pytest.mark.parametrize("shape", [(9, 8, 5), (13, 11, 1), (40, 1, 1), (70, 3, 2), (24, 20, 3),
+                                   (30, 24, 10)])
 def test_elliptic_solve_matches_direct_solve(shape):
     from paper_2510_27447_amd import ionic as I
     n = int(np.prod(shape))
@@ -86,7 +90,8 @@ def test_iteration_count_and_reported_residual():
     assert short["relative_residual"] > rtol
 
 
-@pytest.mark.parametrize("model,shape", [("LR91", (16, 12, 1)), ("TT06", (8, 7, 6))])
+@pytest.mark.parametrize("model,shape", [("LR91", (16, 12, 1)), ("TT06", (8, 7, 6)),
+                                         ("LR91", (24, 20, 3))])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_bidomain_stepping_matches_oracle(model, shape, precision):
     import torch
