@@ -49,10 +49,10 @@ STATE_BYTES = {"fp64": 19 * 8 * 1_000_000, "mixed": (6 * 8 + 13 * 4) * 1_000_000
 
 
 def kernel_source_hash():
-    """Hash of the sources and build flags of the step kernels, which the traffic
-    counters belong to: the step translation units (kernels_*.hip) and the
-    headers they include; the stencil, elliptic and control sources are not
-    part of those kernels."""
+    """Hash of the sources and compile flags of the step kernels, which the
+    traffic counters belong to: the step translation units (kernels_*.hip), the
+    headers they include and the build's flags; the stencil, elliptic,
+    multigrid and control sources are not part of those kernels."""
     h = hashlib.sha1()
     for fn in sorted(os.listdir(CSRC)):
         if (fn.startswith("kernels_") and fn.endswith(".hip")) or fn in (
@@ -61,8 +61,9 @@ def kernel_source_hash():
             h.update(fn.encode())
             with open(os.path.join(CSRC, fn), "rb") as f:
                 h.update(f.read())
-    with open(os.path.join(ROOT, "paper_2510_27447_amd", "build.py"), "rb") as f:
-        h.update(f.read())
+    # the compile flags (not the source list, which other kernels extend)
+    from paper_2510_27447_amd import build as B
+    h.update(repr((B.ARCH, B.FLAGS, sorted(B.OPT.items()), sorted(B.EXTRA.items()))).encode())
     return h.hexdigest()[:16]
 
 
