@@ -497,12 +497,11 @@ static int prepare_preconditioner(ionic_sim* s, const ionic::CgParams& c, void* 
   return IONIC_OK;
 }
 
-// One elliptic solve on stream st (synchronises it); info accumulates.  The
-// device decides convergence after every iteration (iterations after it are
-// launched but do nothing); the host reads that decision after the start and
-// after every batch of iterations: a first batch of expect - 4 when the caller
-// expects about `expect` iterations (the previous solve of a time loop), then
-// batches of 8.  work_bytes has been checked by the caller.
+// One elliptic solve on stream st; info accumulates.  The device decides
+// convergence after every iteration (iterations after it are launched but do
+// nothing); the host reads that decision between batches of iterations (see
+// below).  work_bytes has been checked by the caller; the mean removal at the
+// end is only enqueued.
 static int elliptic_solve_impl(ionic_sim* s, const ionic::CgParams& c, double* u, void* work,
                                double rtol, int max_iter, const Preconditioner& pc,
                                ionic_elliptic_info* info, hipStream_t st, long long expect = 0) {
@@ -520,35 +519,50 @@ static int elliptic_solve_impl(ionic_sim* s, const ionic::CgParams& c, double* u
   IONIC_HIP(ionic::cg_start(c, V, u, w, jacobi, st));
   if (!jacobi) IONIC_HIP(cycle(w.p_k(0), -1));
   IONIC_HIP(ionic::cg_start_sums(c, w, st));
-  ionic::CgCtl ctl{};
-  IONIC_HIP(hipMemcpyAsync(&ctl, w.ctl(), sizeof(ctl), hipMemcpyDeviceToHost, st));
-  IONIC_HIP(hipStreamSynchronize(st));
-  constexpr int kBatch = 8;
-  long long batch = std::max<long long>(jacobi ? kBatch : 1, expect - (jacobi ? 4 : 1));
+  // Iterations in batches.  After each batch one synchronisation reads the
+  // stop flag, b.b and the r.r of the batch's iterations.  The first batch is
+  // the expected count (the previous solve of a time loop; with Jacobi, four
+  // fewer), so a time loop usually synchronises once per solve; launches after
+  // the stop return at once.
+  constexpr int kBatch = 8, kBatchMg = 2;
+  long long batch = jacobi ? std::max<long long>(kBatch, expect - 4)
+                           : std::max<long long>(kBatchMg, expect);
   int k = 0;
-  while (!ctl.done && k < max_iter) {
+  double head[8];                 // the scalars before the per-iteration triples
+  std::vector<double> triples;    // (r.z, p.q, r.r) of iterations k0 .. k
+  int k0 = 0;
+  for (;;) {
+    k0 = k;
     const int until = int(std::min<long long>(max_iter, k + batch));
-    batch = jacobi ? kBatch : 2;
+    batch = jacobi ? kBatch : kBatchMg;
     for (; k < until; ++k) {
       IONIC_HIP(ionic::cg_iteration(c, k, u, w, jacobi, st));
       if (!jacobi) IONIC_HIP(cycle(w.p_k(k + 1), k + 1));
     }
     if (k == max_iter) IONIC_HIP(ionic::cg_end(c, k, w, st));
-    IONIC_HIP(hipMemcpyAsync(&ctl, w.ctl(), sizeof(ctl), hipMemcpyDeviceToHost, st));
+    triples.resize(size_t(3 * (k - k0 + 1)));
+    IONIC_HIP(hipMemcpyAsync(head, w.sc, sizeof(head), hipMemcpyDeviceToHost, st));
+    IONIC_HIP(hipMemcpyAsync(triples.data(), w.rz(k0), triples.size() * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
     IONIC_HIP(hipStreamSynchronize(st));
+    ionic::CgCtl ctl;
+    std::memcpy(&ctl, &head[3], sizeof(ctl));
+    if (ctl.done || k >= max_iter) {
+      // a stop in an earlier batch would have ended the loop there, so the
+      // stopping iteration lies in this batch (or is 0, the first batch's k0)
+      const long long iters = ctl.done ? ctl.iters : k;
+      const double bb = head[0], rr = triples[size_t(3 * (iters - k0) + 2)];
+      const double rel = bb > 0.0 ? std::sqrt(rr / bb) : 0.0;
+      if (info) {
+        info->cg_iterations += iters;
+        info->relative_residual = rel;
+        info->converged = info->converged && rel <= rtol ? 1 : 0;
+      }
+      break;
+    }
   }
-  const long long iters = ctl.done ? ctl.iters : k;
-  double h2[2];  // b.b, r.r of the last iteration
-  IONIC_HIP(hipMemcpyAsync(&h2[0], w.bb(), sizeof(double), hipMemcpyDeviceToHost, st));
-  IONIC_HIP(hipMemcpyAsync(&h2[1], w.rr(iters), sizeof(double), hipMemcpyDeviceToHost, st));
+  // enqueued only: the caller synchronises before u is read
   IONIC_HIP(ionic::cg_remove_mean(c, u, w, st));
-  IONIC_HIP(hipStreamSynchronize(st));
-  const double rel = h2[0] > 0.0 ? std::sqrt(h2[1] / h2[0]) : 0.0;
-  if (info) {
-    info->cg_iterations += iters;
-    info->relative_residual = rel;
-    info->converged = info->converged && rel <= rtol ? 1 : 0;
-  }
   return IONIC_OK;
 }
 
@@ -579,6 +593,7 @@ int ionic_elliptic_solve(ionic_sim* s, const ionic_bidomain_grid* g, double* u_d
   ionic_elliptic_info local{0, 0.0, 1, 0};
   rc = elliptic_solve_impl(s, c, u_dev, work_dev, rtol, max_iter, pc, &local, st);
   if (rc != IONIC_OK) return rc;
+  IONIC_HIP(hipStreamSynchronize(st));
   if (info) *info = local;
   return IONIC_OK;
 }
