@@ -416,7 +416,7 @@ MgPlan mg_plan(long long nx, long long ny, long long nz) {
     if (n <= kMaxCoarsest || !any || p.levels == kMgMaxLevels) break;
     for (int a = 0; a < 3; ++a) d[a] = c[a];
   }
-  // the coarsest level must fit the single-block solve
+  // the coarsest level is inverted densely: at most 512 nodes (a 2 MB inverse)
   const long long* last = p.dims[p.levels - 1];
   p.usable = p.levels >= 2 && last[0] * last[1] * last[2] <= kMaxCoarsest;
   // table layout: per level, per direction K and M (3 each per index), then

@@ -32,9 +32,10 @@ def _buffers(shape, max_iter):
 
 
 # (9, 8, 5) ... (70, 3, 2): at most 512 nodes, Jacobi-preconditioned; (24, 20, 3)
-# and (30, 24, 10): multigrid with 2 and 3 levels
+# and (30, 24, 10): multigrid with 2 and 3 levels; (5000, 1, 1) and (60, 50, 1):
+# multigrid on a cable (5 levels) and a sheet (3 levels), directions with one node
 @pytest.mark.parametrize("shape", [(9, 8, 5), (13, 11, 1), (40, 1, 1), (70, 3, 2), (24, 20, 3),
-                                   (30, 24, 10)])
+                                   (30, 24, 10), (5000, 1, 1), (60, 50, 1)])
 def test_elliptic_solve_matches_direct_solve(shape):
     from paper_2510_27447_amd import ionic as I
     n = int(np.prod(shape))
