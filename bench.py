@@ -63,7 +63,8 @@ def kernel_source_hash():
                 h.update(f.read())
     # the compile flags (not the source list, which other kernels extend)
     from paper_2510_27447_amd import build as B
-    h.update(repr((B.ARCH, B.FLAGS, sorted(B.OPT.items()), sorted(B.EXTRA.items()))).encode())
+    flags = [f.replace(ROOT, ".") for f in B.FLAGS]  # include paths relative to the repository
+    h.update(repr((B.ARCH, flags, sorted(B.OPT.items()), sorted(B.EXTRA.items()))).encode())
     return h.hexdigest()[:16]
 
 
