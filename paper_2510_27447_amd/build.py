@@ -39,6 +39,12 @@ OPT = {}
 # semantics kept, so non-finite states are still detected); results move at
 # the rounding level only, far below the mixed path's tolerance
 EXTRA = {s: ["-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"] for s in STEP_MIXED}
+# the step kernels run at the register limit (one wavefront per SIMD, spills in
+# fp64); the scheduler's own register-pressure trackers place fewer spill and
+# register-copy instructions there (the same results bit for bit; TT06 fp64
+# pass 1.58 -> 1.47 s, mixed 243 -> 240 ms on the 1e6-vertex slab)
+for _s in STEP_FP64 + STEP_MIXED:
+    EXTRA[_s] = EXTRA.get(_s, []) + ["-mllvm", "-amdgpu-use-amdgpu-trackers"]
 ARCH = os.environ.get("IONIC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     "--offload-arch=" + ARCH, "-std=c++20", "-fPIC",
