@@ -32,6 +32,7 @@ STEP_MIXED = ["kernels_%s_mixed%s.hip" % (m, p) for m in ("tt06", "lr91") for p 
 # slowest first, so the parallel build ends sooner
 SOURCES = STEP_FP64 + STEP_MIXED + ["kernels_tt06.hip", "kernels_lr91.hip", "kernels_test.hip",
                                     "control.hip", "diffusion.hip", "elliptic.hip", "multigrid.hip",
+                                    "multigrid_plan.cpp",
                                     "ionic.cpp"]
 # per-source optimisation level (default -O3)
 OPT = {}

@@ -1,7 +1,6 @@
 // The library's Q1 stencil header built as plain host C++ (test only): every
 // node's row applied to a field, its diagonal and its lumped mass.
-#define __device__
-#define __forceinline__ inline
+#include <hip/hip_runtime.h>
 // wavefront shuffles: declared for the lane-shuffle variant of the row, which
 // this host build does not call
 double __shfl_up(double, unsigned int, int);
