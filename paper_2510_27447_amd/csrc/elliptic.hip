@@ -120,6 +120,26 @@ __device__ __forceinline__ Nodes my_nodes(const CgParams& c) {
   return {begin + threadIdx.x, end < c.n ? end : c.n};
 }
 
+// Wavefront passes over consecutive nodes for the lane-shuffle stencil
+// (Q1Node::apply_lanes): each pass covers 62 nodes (lanes 1..62; lanes 0 and
+// 63 hold the nodes on either side).  The trip count is the same for every
+// lane of a wavefront.
+constexpr int kLanesOut = 62;
+
+struct LanePass {
+  long long v;   // this lane's node (may lie outside the chunk: a neighbour)
+  long long vl;  // the node it loads (v clamped to the grid)
+  bool out;      // the lane produces a result for v
+};
+__device__ __forceinline__ LanePass lane_pass(long long first, long long end, long long n) {
+  const int lane = threadIdx.x & 63;
+  LanePass p;
+  p.v = first - 1 + lane;
+  p.vl = p.v < 0 ? 0 : (p.v < n ? p.v : n - 1);
+  p.out = lane >= 1 && lane <= kLanesOut && p.v < end;
+  return p;
+}
+
 // r = b - A_ie U with b = -A_i V; with the Jacobi preconditioner also z = r /
 // diag (the multigrid cycle forms z otherwise); block parts of b.b (part_a),
 // r.z (part_b, Jacobi only) and r.r (part_c)
@@ -133,19 +153,28 @@ __global__ void __launch_bounds__(kThreads)
     w.ctl()->iters = 0;
   }
   double s[3] = {0.0, 0.0, 0.0};  // b.b, r.z, r.r
-  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
-    const Q1Coords x = q1_coords(v, c.nx, c.ny);
+  const long long begin = chunk_id(c) * c.chunk;
+  const long long end = begin + c.chunk < c.n ? begin + c.chunk : c.n;
+  const auto v_of = [V](long long t) { return V[t]; };
+  const auto u_of = [U](long long t) { return U[t]; };
+  for (long long first = begin + (threadIdx.x >> 6) * kLanesOut; first < end;
+       first += kWaves * kLanesOut) {
+    const LanePass lp = lane_pass(first, end, c.n);
+    const Q1Coords x = q1_coords(lp.vl, c.nx, c.ny);
     const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
-    const double b = -node.apply(V, c.si);
-    const double rn = b - node.apply(U, c.sie);
-    w.r[v] = rn;
-    if (jacobi) {
-      const double zn = rn / node.diag(c.sie);
-      w.z[v] = zn;
-      s[1] += rn * zn;
+    double own;
+    const double b = -node.apply_lanes(v_of, c.si, own);
+    const double rn = b - node.apply_lanes(u_of, c.sie, own);
+    if (lp.out) {
+      w.r[lp.v] = rn;
+      if (jacobi) {
+        const double zn = rn / node.diag(c.sie);
+        w.z[lp.v] = zn;
+        s[1] += rn * zn;
+      }
+      s[0] += b * b;
+      s[2] += rn * rn;
     }
-    s[0] += b * b;
-    s[2] += rn * rn;
   }
   if (jacobi) {
     double* const part[3] = {w.part_a, w.part_b, w.part_c};
@@ -182,8 +211,6 @@ __global__ void __launch_bounds__(kThreads) cg_start_sums_kernel(CgParams c, CgW
 // wavefront takes 62 consecutive nodes per pass (lanes 1..62; lanes 0 and 63
 // hold the nodes on either side) so the x-neighbours come from adjacent lanes
 // (Q1Node::apply_lanes): 9 rows per node instead of 27 values.
-constexpr int kLanesOut = 62;
-
 __global__ void __launch_bounds__(kThreads) cg_q_kernel(CgParams c, CgWork w, long long k) {
   if (w.ctl()->done) return;
   double beta = 0.0;
@@ -208,8 +235,8 @@ __global__ void __launch_bounds__(kThreads) cg_q_kernel(CgParams c, CgWork w, lo
   const double* __restrict__ p_old = w.p_k(k - 1);
   double* __restrict__ p_new = w.p_k(k);
   // p_0 = z_0 (p_old holds no direction yet: not read into the value)
-  const bool first = k == 0;
-  const auto p_of = [=](long long t) { return first ? z[t] : z[t] + beta * p_old[t]; };
+  const bool no_prev = k == 0;
+  const auto p_of = [=](long long t) { return no_prev ? z[t] : z[t] + beta * p_old[t]; };
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const long long begin = chunk_id(c) * c.chunk;
   const long long end = begin + c.chunk < c.n ? begin + c.chunk : c.n;
@@ -325,10 +352,18 @@ __global__ void __launch_bounds__(kThreads)
 __global__ void __launch_bounds__(kThreads)
     bidomain_current_kernel(const double* __restrict__ V, const double* __restrict__ U, CgParams c,
                             double inv_h2, double* __restrict__ out) {
-  for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
-    const Q1Coords x = q1_coords(v, c.nx, c.ny);
+  // A_i (v + u) in one pass over the sum (applied to differences, as every row)
+  const long long begin = chunk_id(c) * c.chunk;
+  const long long end = begin + c.chunk < c.n ? begin + c.chunk : c.n;
+  const auto vu_of = [V, U](long long t) { return V[t] + U[t]; };
+  for (long long first = begin + (threadIdx.x >> 6) * kLanesOut; first < end;
+       first += kWaves * kLanesOut) {
+    const LanePass lp = lane_pass(first, end, c.n);
+    const Q1Coords x = q1_coords(lp.vl, c.nx, c.ny);
     const Q1Node node(x.i, x.j, x.k, c.nx, c.ny, c.nz);
-    out[v] = -inv_h2 * (node.apply(V, c.si) + node.apply(U, c.si)) / node.mass();
+    double own;
+    const double a = node.apply_lanes(vu_of, c.si, own);
+    if (lp.out) out[lp.v] = -inv_h2 * a / node.mass();
   }
 }
 
