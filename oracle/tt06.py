@@ -1,12 +1,12 @@
 """ten Tusscher-Panfilov 2006 human ventricular model, epicardial cell
 (oracle; test infrastructure).
 
-Paper, section 2 ("Ten Tusscher model (TP06)"): 19 states (one voltage,
+Paper, section 2 (its subsection on the ten Tusscher model): 19 states (one voltage,
 gating and concentration variables) and 12 currents: fast Na, L-type Ca,
 rapid and slow delayed rectifier K, inward rectifier K, transient outward K,
 plateau K, Na-Ca exchanger, Na-K pump, sarcolemmal Ca pump, background Na and
-background Ca.  The paper uses the epicardial parameter set "as specified in
-the original work" and prints no equations; the forms and constants below are
+background Ca.  The paper takes the epicardial parameter set of the original
+publication and prints no equations; the forms and constants below are
 restated from that publication (ten Tusscher and Panfilov, Am. J. Physiol.
 Heart 291, 2006).
 
