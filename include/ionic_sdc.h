@@ -195,16 +195,33 @@ int ionic_lobatto(int n_nodes, double* c, double* S);
 
 /* Create a simulation over a caller-owned device buffer `state_dev` of
  * `state_bytes` >= ionic_state_bytes(...) bytes (it must outlive the handle)
- * and load the initial state.  x0: n_states x N doubles, row i = state i of
- * every vertex (FP64 SoA, plane order), on the host (x0_on_device = 0) or
- * on the device (1); it is converted into the precision layout on the GPU.
- * x0 must not be NULL.  Enqueues on hip_stream and synchronises it before
- * returning (the host copy of x0 may be released afterwards). */
+ * and load the initial state X = (v, w, c) of every vertex (section 3.3,
+ * equation genODE).
+ *  x0: n_states x N doubles, row i = state i of every vertex (FP64 SoA,
+ *      plane order), on the host (x0_on_device = 0) or on the device (1); it
+ *      is converted into the precision layout on the GPU.
+ *  x0 = NULL: every vertex starts at the model's resting state.  LR91: the
+ *      solution X* of F(X) = 0 without stimulus or diffusion current, found
+ *      on the GPU by Newton's method from V = -84 mV, [Ca]_i = 2e-4 mM and
+ *      every gate at its steady state there.  TT06: the epicardial initial
+ *      conditions printed with the model's publication (the model conserves
+ *      charge, so F(X) = 0 has a one-parameter family of solutions; those
+ *      conditions are the quiescent state of a paced cell).  Test models:
+ *      y = 0.
+ * Host x0: the call synchronises hip_stream before returning, so x0 may be
+ * released afterwards; under IONIC_MIXED it converts through a temporary
+ * device buffer (allocated and freed here, which waits for the device).
+ * Device x0 or NULL: asynchronous, nothing is allocated once a destroyed
+ * handle's statistics block can be reused; a device x0 must stay valid
+ * until the work enqueued on hip_stream has run. */
 int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t state_bytes,
                const double* x0, int x0_on_device, void* hip_stream);
 
-/* Release the handle and its library-owned memory (not the state buffer).
- * Synchronises the device first.  NULL is ignored. */
+/* Release the handle (not the state buffer).  Waits for the work the handle
+ * has enqueued (on every stream it was given; after more than eight
+ * distinct streams, for the device), then keeps its small statistics block
+ * for the next ionic_init on the same device instead of freeing it.  NULL is
+ * ignored. */
 void ionic_destroy(ionic_sim* sim);
 
 /* ---- the hot path ------------------------------------------------------------ */
@@ -348,7 +365,8 @@ int state_readback(ionic_sim* sim, double* out, int64_t first, int64_t count,
  * states unchanged.  Builds initial fields such as spiral waves. Asynchronous. */
 int ionic_gates_to_steady_state(ionic_sim* sim, void* hip_stream);
 
-/* Cumulative statistics since init.  Synchronises the device. */
+/* Cumulative statistics since init.  Both wait for the work the handle has
+ * enqueued (the streams it was given), not for the whole device. */
 int ionic_get_stats(ionic_sim* sim, ionic_stats* out);
 int ionic_reset_stats(ionic_sim* sim);
 

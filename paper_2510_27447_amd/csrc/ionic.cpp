@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -115,7 +116,15 @@ struct DevBlock {
   DevStats stats[kSlots];
   ErrSlot err[kSlots];
   AdaptCtl ctl;
+  double rest[32];  // resting state computed by ionic_init when x0 is NULL
 };
+
+// Blocks of destroyed handles are kept per device and handed to the next
+// ionic_init on that device, so that neither creating nor destroying a handle
+// frees device memory (hipFree waits for the whole device).
+constexpr int kMaxDevices = 64;
+std::mutex g_pool_mu;
+std::vector<DevBlock*> g_pool[kMaxDevices];
 
 }  // namespace
 
@@ -134,6 +143,14 @@ struct ionic_sim {
   int predictor = IONIC_PRED_NEWTON;
   DevBlock* dev = nullptr;  // statistics slots and the adaptive control block
   DevStats* stats = nullptr;
+  int device = 0;           // the HIP device of the state buffer
+  // streams this handle has enqueued work on (ionic_destroy and the stats
+  // calls wait for these only); more than kMaxStreams distinct streams
+  // falls back to waiting for the device
+  static constexpr int kMaxStreams = 8;
+  hipStream_t streams[kMaxStreams] = {};
+  int n_streams = 0;
+  bool many_streams = false;
   // inputs for the batched entry
   bool inputs_set = false;
   double t0 = 0.0, dt = 0.0, t_on = 0.0, t_off = 0.0;
@@ -151,6 +168,26 @@ struct ionic_sim {
 };
 
 namespace {
+
+// Record that work of handle s is enqueued on stream st.
+void touch(ionic_sim* s, hipStream_t st) {
+  for (int i = 0; i < s->n_streams; ++i)
+    if (s->streams[i] == st) return;
+  if (s->n_streams < ionic_sim::kMaxStreams)
+    s->streams[s->n_streams++] = st;
+  else
+    s->many_streams = true;
+}
+
+// Wait until every piece of work the handle has enqueued has completed.
+hipError_t wait_handle(const ionic_sim* s) {
+  if (s->many_streams) return hipDeviceSynchronize();
+  for (int i = 0; i < s->n_streams; ++i) {
+    hipError_t e = hipStreamSynchronize(s->streams[i]);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 void fill_quadrature(int M, LaunchCommon& c) {
   std::memset(&c, 0, sizeof(c));
@@ -269,7 +306,6 @@ int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t
   const size_t need = bytes_of(o, cfg->precision, cfg->n_vertices);
   if (state_bytes < need)
     return fail(IONIC_EINVAL, "state buffer too small: need " + std::to_string(need) + " bytes");
-  if (!x0) return fail(IONIC_EINVAL, "x0 is NULL");
   if (o->params_bytes[0] > 1024 || o->params_bytes[1] > 1024)
     return fail(IONIC_EUNSUPPORTED, "parameter block too large");
 
@@ -287,36 +323,79 @@ int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t
   s->maxit = cfg->newton_maxit;
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  hipError_t e = hipGetDevice(&s->device);
+  if (e != hipSuccess) {
+    delete s;
+    return hip_fail(e, "hipGetDevice");
+  }
+  if (s->device < 0 || s->device >= kMaxDevices) {
+    delete s;
+    return fail(IONIC_EUNSUPPORTED, "device index beyond " + std::to_string(kMaxDevices - 1));
+  }
+  {  // a pooled block of this device, else a new one
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    std::vector<DevBlock*>& pool = g_pool[s->device];
+    if (!pool.empty()) {
+      s->dev = pool.back();
+      pool.pop_back();
+    }
+  }
+  if (!s->dev) {
+    e = hipMalloc(&s->dev, sizeof(DevBlock));
+    if (e != hipSuccess) {
+      s->dev = nullptr;
+      delete s;
+      return hip_fail(e, "hipMalloc(stats)");
+    }
+  }
   auto cleanup = [&](int rc) {
-    if (s->dev) (void)hipFree(s->dev);
+    (void)hipStreamSynchronize(st);
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    g_pool[s->device].push_back(s->dev);
     delete s;
     return rc;
   };
-  hipError_t e = hipMalloc(&s->dev, sizeof(DevBlock));
-  if (e != hipSuccess) {
-    s->dev = nullptr;
-    return cleanup(hip_fail(e, "hipMalloc(stats)"));
-  }
   s->stats = s->dev->stats;
+  touch(s, st);
   e = hipMemsetAsync(s->dev, 0, sizeof(DevBlock), st);
   if (e != hipSuccess) return cleanup(hip_fail(e, "hipMemsetAsync(stats)"));
 
+  if (!x0) {
+    e = o->rest(s->precision, s->p64, s->dev->rest, s->state, s->stride, s->n, st);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "resting state"));
+    *out = s;
+    return IONIC_OK;
+  }
   const double* src = x0;
   double* staging = nullptr;
   const size_t x0_bytes = size_t(o->n_states) * size_t(s->n) * sizeof(double);
+  if (!x0_on_device && s->precision == IONIC_FP64) {
+    // the double layout is the SoA rows of x0 with a padded row stride: copy
+    // them straight into the state buffer
+    e = hipMemcpy2DAsync(s->state, size_t(s->stride) * sizeof(double), x0,
+                         size_t(s->n) * sizeof(double), size_t(s->n) * sizeof(double),
+                         size_t(o->n_states), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return cleanup(hip_fail(e, "copy initial state"));
+    *out = s;
+    return IONIC_OK;
+  }
   if (!x0_on_device) {
     e = hipMalloc(&staging, x0_bytes);
     if (e != hipSuccess) return cleanup(hip_fail(e, "hipMalloc(x0 staging)"));
     e = hipMemcpyAsync(staging, x0, x0_bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) {
+      (void)hipStreamSynchronize(st);
       (void)hipFree(staging);
       return cleanup(hip_fail(e, "hipMemcpyAsync(x0)"));
     }
     src = staging;
   }
   e = o->pack(s->precision, src, s->n, s->state, s->stride, 0, s->n, st);
-  if (e == hipSuccess) e = hipStreamSynchronize(st);
-  if (staging) (void)hipFree(staging);
+  if (staging) {  // the staging buffer is released only after the pack has read it
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(staging);
+  }
   if (e != hipSuccess) return cleanup(hip_fail(e, "pack initial state"));
   *out = s;
   return IONIC_OK;
@@ -324,8 +403,13 @@ int ionic_init(ionic_sim** out, const ionic_config* cfg, void* state_dev, size_t
 
 void ionic_destroy(ionic_sim* s) {
   if (!s) return;
-  (void)hipDeviceSynchronize();
-  if (s->dev) (void)hipFree(s->dev);
+  // the block goes back to the pool once no work of this handle can still
+  // write it
+  (void)wait_handle(s);
+  if (s->dev) {
+    std::lock_guard<std::mutex> g(g_pool_mu);
+    g_pool[s->device].push_back(s->dev);
+  }
   delete s;
 }
 
@@ -344,6 +428,7 @@ int reaction_sdc_step(ionic_sim* s, double t0, double dt, int n_steps, int n_nod
   c.sims[0] = desc_of(s, t0, dt, i_stim_dev, stim_t_on, stim_t_off, i_diff_dev, 0, n_steps,
                       n_sweeps, 0);
   const int blocks = int((s->n + kBlock - 1) / kBlock);
+  touch(s, static_cast<hipStream_t>(hip_stream));
   hipError_t e = s->ops->sdc[s->precision][s->predictor](n_nodes, s->params(), c, blocks,
                                                          static_cast<hipStream_t>(hip_stream));
   if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel");
@@ -368,6 +453,7 @@ int ionic_diffusion_current(ionic_sim* s, const ionic_grid* g, double* i_diff_de
   int rc = check_grid(s, g);
   if (rc != IONIC_OK) return rc;
   if (!i_diff_dev) return fail(IONIC_EINVAL, "i_diff_dev is NULL");
+  touch(s, static_cast<hipStream_t>(hip_stream));
   IONIC_HIP(ionic::diffusion_launch(static_cast<const double*>(s->state), g->nx, g->ny, g->nz,
                                     g->h, g->sigma, i_diff_dev,
                                     static_cast<hipStream_t>(hip_stream)));
@@ -387,6 +473,7 @@ int reaction_diffusion_step(ionic_sim* s, const ionic_grid* g, double t0, double
     return fail(IONIC_EINVAL, "explicit diffusion unstable: dt must be <= h^2 / (2 sigma) = " +
                                   std::to_string(g->h * g->h / (2.0 * g->sigma)));
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  touch(s, st);
   LaunchCommon c;
   fill_quadrature(n_nodes, c);
   c.tol = s->tol;
@@ -587,6 +674,7 @@ int ionic_elliptic_solve(ionic_sim* s, const ionic_bidomain_grid* g, double* u_d
   const ionic::CgParams c = cg_params_of(g, rtol);
   rc = check_elliptic_work(c, work_bytes, max_iter);
   if (rc != IONIC_OK) return rc;
+  touch(s, st);
   Preconditioner pc;
   rc = prepare_preconditioner(s, c, work_dev, max_iter, pc, st);
   if (rc != IONIC_OK) return rc;
@@ -631,6 +719,7 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
   const ionic::SdcLaunch launch = s->ops->sdc[s->precision][s->predictor];
   rc = check_elliptic_work(c, work_bytes, max_iter);
   if (rc != IONIC_OK) return rc;
+  touch(s, st);
   Preconditioner pc;
   rc = prepare_preconditioner(s, c, work_dev, max_iter, pc, st);
   if (rc != IONIC_OK) return rc;
@@ -687,6 +776,7 @@ int reaction_sdc_adaptive(ionic_sim* s, double t0, double t_end, double dt_init,
   if (work_dev == s->state) return fail(IONIC_EINVAL, "work_dev must differ from the state buffer");
 
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  touch(s, st);
   constexpr double kDtMin = 1e-12;
   AdaptCtl* ctl = &s->dev->ctl;
   ErrSlot* err = s->dev->err;
@@ -799,7 +889,10 @@ int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_si
     hipError_t e = s0->ops->sdc[s0->precision][s0->predictor](s0->M, s0->params(), c, blocks, st);
     if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (batch)");
   }
-  for (int k = 0; k < n_sims; ++k) sims[k]->step_offset += n_steps[k];
+  for (int k = 0; k < n_sims; ++k) {
+    sims[k]->step_offset += n_steps[k];
+    touch(sims[k], st);
+  }
   return IONIC_OK;
 }
 
@@ -811,6 +904,7 @@ int state_readback(ionic_sim* s, double* out, int64_t first, int64_t count, int 
     return fail(IONIC_EINVAL, "vertex range out of bounds");
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
   if (count == 0) return IONIC_OK;
+  touch(s, st);
   const size_t bytes = size_t(s->ops->n_states) * size_t(count) * sizeof(double);
   if (out_on_device) {
     IONIC_HIP(s->ops->unpack(s->precision, s->state, s->stride, first, count, out, count, st));
@@ -829,6 +923,7 @@ int state_readback(ionic_sim* s, double* out, int64_t first, int64_t count, int 
 
 int ionic_gates_to_steady_state(ionic_sim* s, void* hip_stream) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  touch(s, static_cast<hipStream_t>(hip_stream));
   IONIC_HIP(s->ops->steady(s->precision, s->params(), s->state, s->stride, s->n,
                            static_cast<hipStream_t>(hip_stream)));
   return IONIC_OK;
@@ -838,8 +933,11 @@ int ionic_get_stats(ionic_sim* s, ionic_stats* out) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
   if (!out) return fail(IONIC_EINVAL, "out is NULL");
   std::vector<DevStats> d(kSlots);
-  IONIC_HIP(hipDeviceSynchronize());
-  IONIC_HIP(hipMemcpy(d.data(), s->stats, sizeof(DevStats) * kSlots, hipMemcpyDeviceToHost));
+  IONIC_HIP(wait_handle(s));
+  const hipStream_t cs = s->n_streams ? s->streams[0] : nullptr;
+  IONIC_HIP(hipMemcpyAsync(d.data(), s->stats, sizeof(DevStats) * kSlots, hipMemcpyDeviceToHost,
+                           cs));
+  IONIC_HIP(hipStreamSynchronize(cs));
   std::memset(out, 0, sizeof(*out));
   for (const DevStats& x : d) {  // fold the slots
     out->vertex_steps += int64_t(x.vertex_steps);
@@ -854,9 +952,10 @@ int ionic_get_stats(ionic_sim* s, ionic_stats* out) {
 
 int ionic_reset_stats(ionic_sim* s) {
   if (!s) return fail(IONIC_EINVAL, "sim is NULL");
-  IONIC_HIP(hipDeviceSynchronize());
-  IONIC_HIP(hipMemset(s->stats, 0, sizeof(DevStats) * kSlots));
-  IONIC_HIP(hipDeviceSynchronize());
+  IONIC_HIP(wait_handle(s));
+  const hipStream_t cs = s->n_streams ? s->streams[0] : nullptr;
+  IONIC_HIP(hipMemsetAsync(s->stats, 0, sizeof(DevStats) * kSlots, cs));
+  IONIC_HIP(hipStreamSynchronize(cs));
   return IONIC_OK;
 }
 
@@ -868,6 +967,7 @@ int ionic_debug_jacobian(ionic_sim* s, int64_t vertex, double i_stim, double i_d
   const int n = s->ops->n_states;
   const size_t bytes = size_t(n + n * n) * sizeof(double);
   hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  touch(s, st);
   double* tmp = nullptr;
   IONIC_HIP(hipMalloc(&tmp, bytes));
   std::vector<double> host(size_t(n + n * n));

@@ -42,6 +42,10 @@ struct ModelOps {
                        long long count, double* dst, long long ld, hipStream_t st);
   hipError_t (*steady)(int prec, const void* params, void* state, long long stride, long long n,
                        hipStream_t st);
+  // resting state (computed in double into rest_out, N doubles) broadcast to
+  // every vertex of the state in precision `prec`
+  hipError_t (*rest)(int prec, const void* params64, double* rest_out, void* state,
+                     long long stride, long long n, hipStream_t st);
   hipError_t (*debug_jac)(int prec, const void* params, const void* state, long long stride,
                           long long v, double stim, double diff, double* out, hipStream_t st);
 };

@@ -82,6 +82,21 @@ struct OpsImpl {
                          stride, n);
     return hipGetLastError();
   }
+  static hipError_t rest(int prec, const void* params64, double* rest_out, void* state,
+                         long long stride, long long n, hipStream_t st) {
+    hipLaunchKernelGGL((rest_state_kernel<Model>), dim3(1), dim3(64), 0, st,
+                       *static_cast<const typename Model::template Params<double>*>(params64),
+                       rest_out);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (prec == 0)
+      hipLaunchKernelGGL((broadcast_kernel<Model, Fp64>), dim3(grid(n)), dim3(kAuxBlock), 0, st,
+                         rest_out, state, stride, n);
+    else
+      hipLaunchKernelGGL((broadcast_kernel<Model, Mixed>), dim3(grid(n)), dim3(kAuxBlock), 0, st,
+                         rest_out, state, stride, n);
+    return hipGetLastError();
+  }
   static hipError_t debug_jac(int prec, const void* params, const void* state, long long stride,
                               long long v, double stim, double diff, double* out, hipStream_t st) {
     if (prec == 0)
@@ -125,6 +140,7 @@ struct OpsImpl {
     o.pack = &pack;
     o.unpack = &unpack;
     o.steady = &steady;
+    o.rest = &rest;
     o.debug_jac = &debug_jac;
     return o;
   }

@@ -31,6 +31,13 @@ struct LR91 {
   // Newton stop scale s_i = max(|Y_i|, SCALE_i)
   static constexpr double SCALE[N] = {100.0, 1e-4, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0};
 
+  // Resting state loaded by ionic_init when no initial state is given: the
+  // solution X* of F(X) = 0 (no stimulus, no diffusion current), found by
+  // Newton's method from V = -84 mV, [Ca]_i = 2e-4 mM and every gate at its
+  // steady state at that V (the gate entries below are replaced by it).
+  static constexpr bool REST_BY_NEWTON = true;
+  static constexpr double REST_GUESS[N] = {-84.0, 2e-4, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+
   // Overridable raw parameters, in this order.
   static constexpr int N_PARAMS = 15;
   static constexpr const char* PARAM_NAMES[N_PARAMS] = {

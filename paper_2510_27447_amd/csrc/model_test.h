@@ -14,6 +14,8 @@ struct TestLinear {
   static constexpr int N64 = 1;
   static constexpr uint32_t ROW[N] = {1u};
   static constexpr double SCALE[N] = {1.0};
+  static constexpr bool REST_BY_NEWTON = false;  // y = 0 when no initial state is given
+  static constexpr double REST_GUESS[N] = {0.0};
   static constexpr int N_PARAMS = 2;
   static constexpr const char* PARAM_NAMES[N_PARAMS] = {"lam", "b"};
   static constexpr double PARAM_DEFAULTS[N_PARAMS] = {-1.0, 0.0};
@@ -38,6 +40,8 @@ struct TestLogistic {
   static constexpr int N64 = 1;
   static constexpr uint32_t ROW[N] = {1u};
   static constexpr double SCALE[N] = {1.0};
+  static constexpr bool REST_BY_NEWTON = false;  // y = 0 when no initial state is given
+  static constexpr double REST_GUESS[N] = {0.0};
   static constexpr int N_PARAMS = 1;
   static constexpr const char* PARAM_NAMES[N_PARAMS] = {"rate"};
   static constexpr double PARAM_DEFAULTS[N_PARAMS] = {1.0};

@@ -2,10 +2,9 @@
 // device form (paper section 2, "Ten Tusscher model (TP06)").
 //
 // 19 states; 12 currents: I_Na, I_CaL, I_Kr, I_Ks, I_K1, I_to, I_pK, I_NaCa,
-// I_NaK, I_pCa, I_bNa, I_bCa.  The paper uses the epicardial set "as
-// specified in the original work" without printing it; the forms and
-// constants are restated from that publication (Am. J. Physiol. Heart 291,
-// 2006).  Readings shared with the reference implementation used for testing:
+// I_NaK, I_pCa, I_bNa, I_bCa.  The paper takes the epicardial parameter set
+// of the model's publication and does not print it; the forms and constants
+// are restated from that publication (Am. J. Physiol. Heart 291, 2006).  Readings shared with the reference implementation used for testing:
 // free [Ca]_i, [Ca]_SR, [Ca]_SS as states with rapid-equilibrium buffering
 // factors; dV/dt = -(I_ion + I_stim) + I_diff with C_m = 1 uF/cm^2 and
 // currents in pA/pF; stimulus and diffusion current carried by K+ in d[K]_i/dt;
@@ -50,6 +49,15 @@ struct TT06 {
 
   static constexpr double SCALE[N] = {100.0, 1e-4, 1.0, 1e-4, 10.0, 100.0, 1.0, 1.0, 1.0, 1.0,
                                       1.0,   1.0,  1.0, 1.0,  1.0,  1.0,   1.0, 1.0, 1.0};
+
+  // Resting state loaded by ionic_init when no initial state is given: the
+  // epicardial initial conditions printed with the model's publication (the
+  // quiescent state of a paced cell).  F(X) = 0 is not used: the model
+  // conserves charge exactly, so its equilibria form a one-parameter family.
+  static constexpr bool REST_BY_NEWTON = false;
+  static constexpr double REST_GUESS[N] = {
+      -85.23, 0.000126, 3.64,    0.00036, 8.604,  136.89, 0.00172,  0.7444,   0.7045, 0.00621,
+      0.4712, 0.0095,   2.42e-8, 0.999998, 3.373e-5, 0.7888, 0.9755, 0.9953, 0.9073};
 
   static constexpr int N_PARAMS = 47;
   static constexpr const char* PARAM_NAMES[N_PARAMS] = {

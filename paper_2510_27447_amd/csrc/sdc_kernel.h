@@ -353,7 +353,11 @@ __global__ void __launch_bounds__(kBlock)
   for (int step = 0; step < sd.n_steps; ++step) {
     const double t_mid = t0 + (double(sd.step_offset + step) + 0.5) * dt;
     const TE stim = (sd.t_on <= t_mid && t_mid < sd.t_off) ? stim_amp : TE(0);
-    TE F0[N];  // F(X_n), needed by the sweeps; every predictor evaluates F there first
+    // F(X_n), needed by the sweeps; every predictor evaluates F there first.  The
+    // Newton predictor takes it from its first iteration through a select, so it
+    // starts defined.
+    TE F0[N];
+    static_for<N>([&](auto I) { F0[I] = TE(0); });
 
     if constexpr (Pred == kPredRos2) {
       // ---- predictor: one ROS2 step on each sub-interval
@@ -622,6 +626,77 @@ __global__ void steady_gates_kernel(const typename Model::template Params<typena
     if constexpr (i >= Model::N64) L::template at<i>(x) = xe[i];
   });
   L::store(x, state, stride, v);
+}
+
+// Resting state of the model on one lane, written to out[0..N): with
+// Model::REST_BY_NEWTON, Newton's method on F(X) = 0 (no stimulus, no
+// diffusion current) from REST_GUESS with the gates at their steady state,
+// each iteration a dense solve with partial pivoting, until the scaled update
+// max_i |delta_i| / max(|X_i|, SCALE_i) falls below 1e-15 (at most 50
+// iterations); otherwise REST_GUESS itself.
+template <class Model>
+__global__ void rest_state_kernel(const typename Model::template Params<double> p, double* out) {
+  constexpr int N = Model::N;
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double x[N];
+  for (int i = 0; i < N; ++i) x[i] = Model::REST_GUESS[i];
+  if constexpr (Model::REST_BY_NEWTON) {
+    Model::template steady_gates<double>(p, x);
+    for (int it = 0; it < 50; ++it) {
+      double f[N], A[N][N + 1];
+      double J[N * N];
+      for (int k = 0; k < N * N; ++k) J[k] = 0.0;
+      SinkDense<Model, double> s{f, J};
+      call_rhs_FJ<Model, double>(p, 0.0, 0.0, s, x, std::make_index_sequence<N>{});
+      for (int i = 0; i < N; ++i) {
+        for (int k = 0; k < N; ++k) A[i][k] = J[i * N + k];
+        A[i][N] = -f[i];
+      }
+      for (int c = 0; c < N; ++c) {  // elimination with partial pivoting
+        int pr = c;
+        for (int i = c + 1; i < N; ++i)
+          if (fabs(A[i][c]) > fabs(A[pr][c])) pr = i;
+        if (A[pr][c] == 0.0) break;
+        for (int k = 0; k <= N; ++k) {
+          const double t = A[c][k];
+          A[c][k] = A[pr][k];
+          A[pr][k] = t;
+        }
+        for (int i = c + 1; i < N; ++i) {
+          const double l = A[i][c] / A[c][c];
+          for (int k = c; k <= N; ++k) A[i][k] -= l * A[c][k];
+        }
+      }
+      double delta[N], worst = 0.0;
+      for (int i = N - 1; i >= 0; --i) {
+        double acc = A[i][N];
+        for (int k = i + 1; k < N; ++k) acc -= A[i][k] * delta[k];
+        delta[i] = acc / A[i][i];
+      }
+      for (int i = 0; i < N; ++i) {
+        x[i] += delta[i];
+        const double sc = fmax(fabs(x[i]), Model::SCALE[i]);
+        worst = fmax(worst, fabs(delta[i]) / sc);
+      }
+      if (!(worst >= 1e-15)) break;  // converged (or non-finite: stop)
+    }
+  }
+  for (int i = 0; i < N; ++i) out[i] = x[i];
+}
+
+// Every vertex of [0, n) set to the one state x (N doubles), in the precision layout.
+template <class Model, class Prec>
+__global__ void broadcast_kernel(const double* __restrict__ x, void* state, long long stride,
+                                 long long n) {
+  using L = Layout<Model, Prec>;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= n) return;
+  typename L::Node node;
+  static_for<Model::N>([&](auto I) {
+    constexpr int i = I;
+    L::template at<i>(node) = x[i];
+  });
+  L::store(node, state, stride, v);
 }
 
 template <class Model, class Prec>

@@ -248,9 +248,13 @@ def make_config(model, n_vertices, precision=FP64, newton_tol=1e-10, newton_maxi
 
 
 def ionic_init(cfg, state_ptr, state_bytes, x0, x0_on_device=False, stream=None):
-    """Returns the opaque handle (an int).  x0: host numpy (n, N) float64 or a device address."""
+    """Returns the opaque handle (an int).  x0: host numpy (n, N) float64, a device
+    address / tensor (x0_on_device=True), or None for the model's resting state."""
     h = c_void_p()
-    if x0_on_device:
+    if x0 is None:
+        x0p = None
+        keep = None
+    elif x0_on_device:
         x0p = _ptr(x0)
         keep = None
     else:
@@ -377,20 +381,34 @@ class Simulation:
     """One simulation: a device state buffer (torch uint8 tensor) plus its handle."""
 
     def __init__(self, model, x0, precision=FP64, newton_tol=1e-10, newton_maxit=10, params=None,
-                 stream=None, device="cuda"):
+                 stream=None, device="cuda", n_vertices=None):
+        """x0: host (n_states, N) array, a device float64 tensor of that shape
+        (converted on the GPU, asynchronously), or None with n_vertices for the
+        model's resting state."""
         import torch
         model = MODEL_IDS.get(model, model)
         precision = PRECISIONS.get(precision, precision)
-        x0 = np.asarray(x0, dtype=np.float64)
         self.model, self.precision = model, precision
         self.n_states = ionic_n_states(model)
-        if x0.ndim != 2 or x0.shape[0] != self.n_states:
-            raise ValueError("x0 must have shape (%d, N)" % self.n_states)
-        self.n = x0.shape[1]
+        on_device = isinstance(x0, torch.Tensor) and x0.is_cuda
+        if x0 is None:
+            if n_vertices is None:
+                raise ValueError("x0 = None needs n_vertices")
+            self.n = int(n_vertices)
+        else:
+            if on_device:
+                if x0.dtype != torch.float64 or not x0.is_contiguous():
+                    raise ValueError("a device x0 must be a contiguous float64 tensor")
+            else:
+                x0 = np.asarray(x0, dtype=np.float64)
+            if x0.ndim != 2 or x0.shape[0] != self.n_states:
+                raise ValueError("x0 must have shape (%d, N)" % self.n_states)
+            self.n = int(x0.shape[1])
         nbytes = ionic_state_bytes(model, precision, self.n)
         self.state = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.config = make_config(model, self.n, precision, newton_tol, newton_maxit, params)
-        self.handle = ionic_init(self.config, self.state.data_ptr(), nbytes, x0, False, stream)
+        self._x0_keep = x0 if on_device else None  # alive until the conversion has run
+        self.handle = ionic_init(self.config, self.state.data_ptr(), nbytes, x0, on_device, stream)
 
     def step(self, t0, dt, n_steps, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0, stim_t_off=0.0,
              i_diff=None, stream=None):

@@ -8,11 +8,12 @@ tail and random interior ones.
 C1 LR91 fp64 (4096 vertices, 1000 steps), C2 TT06 fp64 (100^3, 500 steps),
 C3 the same in mixed precision (<= 1e-4 against the fp64 oracle, max and RMS
 reported for V and every concentration), C4 TT06 spiral (200^3, 1000 steps,
-4 nodes, diffusion input redrawn every 50 steps) in both precisions."""
+4 nodes, diffusion input redrawn every 50 steps) in both precisions.  Every
+state is compared, gates included."""
 import numpy as np
 import pytest
 
-from gpu_helpers import rel_errors, run_gpu, run_oracle, say
+from gpu_helpers import MODEL_OF, rel_errors, run_gpu, run_oracle, say
 from paper_2510_27447_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
@@ -37,37 +38,52 @@ def oracle_on(w, idx, key):
     return _ORACLE[key]
 
 
-def check(w, idx, key, tol_v, tol_conc, n64):
+def check(w, idx, key):
+    """Every state of the sampled vertices against the oracle.  fp64: V within
+    1e-10 of max|V_ref|, every other state within 1e-9 of its scale
+    max(max|X_ref,i|, s_i) (s_i the Newton scale); mixed: V and the fp64-held
+    concentrations within 1e-4, the fp32 gates within 1e-3."""
+    mdl = MODEL_OF[w.model]
+    n64 = len(mdl.fp64_states)
     say("case", w.name, "N", w.n, "sample", len(idx))
     Xg, st = run_gpu(w)
     say("  stats", st)
     Xo = oracle_on(w, idx, key)
-    err = rel_errors(Xg[:, idx], Xo, list(range(w.x0.shape[0])))
-    say("  V max %.3e rms %.3e" % err[0], " fp64-held:", ["%.2e" % err[i][0] for i in range(n64)])
+    Xs = Xg[:, idx]
+    err = rel_errors(Xs, Xo, list(range(w.x0.shape[0])))
+    scale = np.maximum(np.max(np.abs(Xo), axis=1), mdl.newton_scale)
+    serr = np.max(np.abs(Xs - Xo), axis=1) / scale
+    say("  V max %.3e rms %.3e" % err[0], " all states (scaled max):",
+        " ".join("%s %.1e" % (nm, e) for nm, e in zip(mdl.state_names, serr)))
     assert st["n_nonfinite"] == 0
     assert st["vertex_steps"] == w.n * w.n_steps
-    assert err[0][0] <= tol_v
-    for i in range(1, n64):
-        assert err[i][0] <= tol_conc, i
+    if w.precision == "fp64":
+        assert err[0][0] <= 1e-10
+        bad = [(nm, e) for nm, e in zip(mdl.state_names, serr) if not e <= 1e-9]
+    else:
+        assert err[0][0] <= 1e-4
+        bad = [(nm, e) for i, (nm, e) in enumerate(zip(mdl.state_names, serr))
+               if not e <= (1e-4 if i < n64 else 1e-3)]
+    assert not bad, bad
     return err
 
 
 def test_c1_lr91_fp64():
     w = W.c1_lr91()
     idx = sample(w, 48, 80)
-    check(w, idx, "c1", 1e-10, 1e-9, 2)
+    check(w, idx, "c1")
 
 
 def test_c2_tt06_fp64():
     w = W.c2_tt06()
     idx = sample(w, 16, 32)
-    check(w, idx, "c2", 1e-10, 1e-9, 6)
+    check(w, idx, "c2")
 
 
 def test_c3_tt06_mixed():
     w = W.c3_tt06_mixed()
     idx = sample(w, 16, 32)
-    err = check(w, idx, "c2", 1e-4, 1e-4, 6)   # against the fp64 oracle of C2
+    err = check(w, idx, "c2")   # against the fp64 oracle of C2
     say("  C3 error vs fp64 oracle (max, rms):", {k: err[k] for k in range(6)})
 
 
@@ -76,5 +92,4 @@ def test_c4_tt06_spiral(precision):
     w = W.c4_tt06_spiral(precision=precision)
     rng = np.random.Generator(np.random.PCG64(3))
     idx = np.array(sorted(set(rng.choice(w.n, 14, replace=False).tolist()) | {0, w.n - 1}))
-    tol = 1e-10 if precision == "fp64" else 1e-4
-    check(w, idx, "c4", tol, 100 * tol, 6)
+    check(w, idx, "c4")

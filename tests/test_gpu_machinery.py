@@ -167,3 +167,36 @@ def test_steady_gates_match_oracle():
     ss = ot.gate_steady_state(V, x0[3])
     for k, v in ss.items():
         np.testing.assert_allclose(X[ot.STATE_NAMES.index(k)], v, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("model", ["LR91", "TT06"])
+def test_init_without_x0_loads_rest_state(model, precision):
+    """ionic_init(x0 = NULL): LR91 at the oracle's resting state X* (F(X*) = 0, the
+    GPU's own Newton solve), TT06 at the published initial conditions; every
+    vertex (a ragged 130) holds it, in the precision layout."""
+    from oracle import rest as orest
+    from oracle import tt06 as ot
+    ref = orest.lr91_rest() if model == "LR91" else ot.published_initial()
+    s = I.Simulation(model, None, precision=precision, n_vertices=130)
+    X = s.readback()
+    s.close()
+    assert X.shape == (len(ref), 130)
+    n64 = 2 if model == "LR91" else 6
+    for i, r in enumerate(ref):
+        tol = 1e-12 if (precision == "fp64" or i < n64) else 6e-8  # fp32 gates: one rounding
+        np.testing.assert_allclose(X[i], r, rtol=tol, atol=1e-300, err_msg=str(i))
+    if model == "TT06" and precision == "fp64":
+        assert np.array_equal(X, np.tile(np.asarray(ref)[:, None], (1, 130)))
+
+
+def test_init_from_device_x0_equals_host_x0():
+    """The asynchronous device-x0 path loads exactly what the host path loads."""
+    import torch
+    x0, _, _ = _tissue("TT06", 150, 9, "mixed")
+    for precision in ("fp64", "mixed"):
+        a = I.Simulation("TT06", x0, precision=precision)
+        b = I.Simulation("TT06", torch.as_tensor(x0).cuda(), precision=precision)
+        assert np.array_equal(a.readback(), b.readback())
+        a.close()
+        b.close()

@@ -45,7 +45,7 @@ def test_fp64_matches_oracle(model, M, K):
 
 
 @pytest.mark.parametrize("model", ["LR91", "TT06"])
-@pytest.mark.parametrize("M,K", [(2, 1), (3, 3), (4, 3)])
+@pytest.mark.parametrize("M,K", [(2, 1), (3, 2), (3, 3), (4, 3)])
 def test_mixed_matches_fp64_oracle(model, M, K):
     w = small_workload(model, "mixed", M, K)
     say("case", w.name)
