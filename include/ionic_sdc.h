@@ -360,6 +360,21 @@ int reaction_sdc_step_batch(ionic_sim* const* sims, const int* n_steps, int n_si
 int state_readback(ionic_sim* sim, double* out, int64_t first, int64_t count,
                    int out_on_device, void* hip_stream);
 
+/* state_readback into a host buffer without allocating anything, for
+ * callers that cannot allocate device memory (code that runs while a HIP
+ * graph is being captured, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, result and synchronisation as
+ * state_readback with out_on_device = 0 (out: n_states x count doubles on
+ * the host, row i = state i).  The widened values are staged in a static
+ * device array of 8 MiB that the library holds on every GPU it runs on until
+ * the process ends: n_states * count * 8 bytes must not exceed 8 MiB (TT06:
+ * 55,188 vertices; LR91: 131,072), else IONIC_EINVAL before any HIP call.
+ * The current device must be the handle's.  All calls on one GPU share that
+ * array, so calls that overlap in time on one GPU (other threads, other
+ * streams) race; serialise them. */
+int state_readback_noalloc(ionic_sim* sim, double* out, int64_t first, int64_t count,
+                           void* hip_stream);
+
 /* Set every voltage-dependent gate to its steady state at the vertex's
  * current V (TT06: fCass to its steady state at the current CaSS); other
  * states unchanged.  Builds initial fields such as spiral waves. Asynchronous. */

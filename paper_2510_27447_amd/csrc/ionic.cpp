@@ -126,6 +126,34 @@ constexpr int kMaxDevices = 64;
 std::mutex g_pool_mu;
 std::vector<DevBlock*> g_pool[kMaxDevices];
 
+// Staging of state_readback_noalloc: one file-scope device array per GPU,
+// held until the process ends.  On the host its name is only a stand-in: the
+// array's address on a device comes from hipGetSymbolAddress, taken once per
+// device with that device current (scratch_on_current_device).
+constexpr size_t kScratchBytes = size_t(8) << 20;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+namespace {
+
+// Device address of `scratch` on the current device (0 = OK).
+int scratch_on_current_device(int device, double** out) {
+  std::lock_guard<std::mutex> g(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(IONIC_EHIP, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_ptr[device] = p;
+  }
+  *out = static_cast<double*>(g_scratch_ptr[device]);
+  return IONIC_OK;
+}
+
 }  // namespace
 
 struct ionic_sim {
@@ -918,6 +946,34 @@ int state_readback(ionic_sim* s, double* out, int64_t first, int64_t count, int 
   if (e == hipSuccess) e = hipStreamSynchronize(st);
   (void)hipFree(tmp);
   if (e != hipSuccess) return hip_fail(e, "state_readback");
+  return IONIC_OK;
+}
+
+int state_readback_noalloc(ionic_sim* s, double* out, int64_t first, int64_t count,
+                           void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (!out) return fail(IONIC_EINVAL, "out is NULL");
+  if (first < 0 || count < 0 || first + count > s->n)
+    return fail(IONIC_EINVAL, "vertex range out of bounds");
+  if (count == 0) return IONIC_OK;
+  const size_t bytes = size_t(s->ops->n_states) * size_t(count) * sizeof(double);
+  if (bytes > kScratchBytes)
+    return fail(IONIC_EINVAL, "readback of " + std::to_string(bytes) + " bytes exceeds the " +
+                                  std::to_string(kScratchBytes) + "-byte static staging buffer (" +
+                                  std::to_string(kScratchBytes / (size_t(s->ops->n_states) * 8)) +
+                                  " vertices of this model)");
+  int dev = -1;
+  IONIC_HIP(hipGetDevice(&dev));
+  if (dev != s->device)
+    return fail(IONIC_EINVAL, "the current device is not the handle's device");
+  double* stage = nullptr;
+  int rc = scratch_on_current_device(dev, &stage);
+  if (rc != IONIC_OK) return rc;
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  touch(s, st);
+  IONIC_HIP(s->ops->unpack(s->precision, s->state, s->stride, first, count, stage, count, st));
+  IONIC_HIP(hipMemcpyAsync(out, stage, bytes, hipMemcpyDeviceToHost, st));
+  IONIC_HIP(hipStreamSynchronize(st));
   return IONIC_OK;
 }
 

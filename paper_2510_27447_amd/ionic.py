@@ -132,6 +132,7 @@ _SIGNATURES = {
                                  c_double, c_void_p]),
     "reaction_sdc_step_batch": (c_int, [POINTER(c_void_p), POINTER(c_int), c_int, c_void_p]),
     "state_readback": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_int, c_void_p]),
+    "state_readback_noalloc": (c_int, [c_void_p, c_void_p, c_int64, c_int64, c_void_p]),
     "ionic_gates_to_steady_state": (c_int, [c_void_p, c_void_p]),
     "ionic_get_stats": (c_int, [c_void_p, POINTER(ionic_stats)]),
     "ionic_reset_stats": (c_int, [c_void_p]),
@@ -352,6 +353,14 @@ def state_readback(handle, n_states, first, count, out=None, stream=None):
         return out
     host = np.empty((n_states, count), dtype=np.float64)
     _check(lib().state_readback(handle, host.ctypes.data, first, count, 0, _stream(stream)))
+    return host
+
+
+def state_readback_noalloc(handle, n_states, first, count, stream=None):
+    """Host (n_states, count) float64 array, staged through the library's
+    static device buffer (no allocation; at most 8 MiB per call)."""
+    host = np.empty((n_states, count), dtype=np.float64)
+    _check(lib().state_readback_noalloc(handle, host.ctypes.data, first, count, _stream(stream)))
     return host
 
 
