@@ -41,6 +41,12 @@ LR91_FLOPS = {"F": 232, "FJ": 465, "solve": 75, "resolve": 40}
 TT06_RL_FLOPS = {"gate_step_first": 568, "gate_step": 335, "core_FJ": 572, "core_solve": 174}
 PEAK_TFLOPS = {"fp64": 78.6, "mixed": 157.3}   # MI355X vector fp64 / fp32 (published)
 HBM_PEAK_GBS = 8000.0
+# Operation counts by kind (same source as above): the transcendental kinds
+# and divisions of one F and one F+J evaluation, and the pivot reciprocals of
+# one static solve (one per state).
+TT06_KINDS = {"F": {"div": 72, "mul": 245, "add": 178, "exp": 52, "log": 4, "expm1": 1, "sqrt": 1},
+              "FJ": {"div": 77, "mul": 813, "add": 302, "exp": 52, "log": 4, "expm1": 1, "sqrt": 1}}
+TT06_N, TT06_N64 = 19, 6
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(ROOT, "paper_2510_27447_amd", "csrc")
@@ -69,7 +75,7 @@ def kernel_source_hash():
 
 
 SHORT_FLAGS = ("--no-serving", "--no-cpu", "--no-ros2", "--no-rl", "--no-diffusion",
-               "--no-bidomain")
+               "--no-bidomain", "--no-c4", "--no-micro")
 
 
 def traffic_from_counters(fetch_csv, write_csv):
@@ -173,11 +179,50 @@ def flops_per_launch_rl(ev, rl, n_states, n_core, vertex_steps, M, K, newton_ite
             + newton_iters * (rl["core_FJ"] + rl["core_solve"] + 6 * n_core))
 
 
+def work_split(vertex_steps, M, K, newton_iters, precision, ev=TT06_FLOPS, kinds=TT06_KINDS,
+               n=TT06_N, n64=TT06_N64):
+    """Algorithmic work of one Newton-predictor launch split by the unit that
+    executes it (the t_min decomposition W64/P64 + W32/P32 + Wtr/Ptr).
+
+    fp64 path: Wtr = the exp/log/expm1 calls (software sequences in double),
+    W64 = every other flop (divisions, square roots and pivot reciprocals
+    count one each).  Mixed path: Wtr = every exp, log, expm1, sqrt,
+    division and pivot reciprocal of the fp32 evaluations and solves (each one
+    hardware transcendental instruction), W32 = their adds and multiplies,
+    W64 = the Newton residuals and the SDC quadrature and residuals (formed in
+    double) and the updates of the n64 double-held states; the updates of the
+    fp32 states and the stop tests are W32."""
+    F_evals = vertex_steps * K * (M - 2)
+    FJ_evals = newton_iters + vertex_steps * K * (M - 1)
+    solve_rcp = n
+    solve_arith = ev["solve"] - solve_rcp
+    sw_nodes = vertex_steps * K * (M - 1)
+    if precision == "fp64":
+        tr = lambda c: c["exp"] + c["log"] + c["expm1"]
+        wtr = F_evals * tr(kinds["F"]) + FJ_evals * tr(kinds["FJ"])
+        total = flops_per_launch(ev, n, vertex_steps, M, K, newton_iters)
+        return {"W64": total - wtr, "W32": 0.0, "Wtr": wtr}
+    tr = lambda c: c["exp"] + c["log"] + c["expm1"] + c["sqrt"] + c["div"]
+    ar = lambda c: c["add"] + c["mul"]
+    wtr = F_evals * tr(kinds["F"]) + FJ_evals * (tr(kinds["FJ"]) + solve_rcp)
+    w32 = (F_evals * ar(kinds["F"]) + FJ_evals * (ar(kinds["FJ"]) + solve_arith)
+           + newton_iters * (2 * n + (n - n64)) + sw_nodes * (n - n64))
+    w64 = newton_iters * (3 * n + n64) + sw_nodes * ((2 * M + 2) * n + n64)
+    return {"W64": w64, "W32": w32, "Wtr": wtr}
+
+
+def t_min(split, precision, rates):
+    """Lower bound on a launch's time from its work split and unit rates
+    (flop/s for P64 and P32, operations/s for the transcendentals)."""
+    ptr = rates["exp64"] if precision == "fp64" else rates["trans32"]
+    return split["W64"] / rates["P64"] + split["W32"] / rates["P32"] + split["Wtr"] / ptr
+
+
 def state_bytes_per_vertex(precision):
     return 19 * 8 if precision == "fp64" else 6 * 8 + 13 * 4
 
 
-def run_pass_set(I, torch, w, steps, warmup, predictor="newton"):
+def run_pass_set(I, torch, w, steps, warmup, predictor="newton", sample=None, rates=None):
     sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
                        newton_maxit=w.newton_maxit)
     sim.set_predictor(predictor)
@@ -209,7 +254,10 @@ def run_pass_set(I, torch, w, steps, warmup, predictor="newton"):
     wall = time.perf_counter() - t0
     kernel_ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     st = sim.stats()
-    V = sim.readback()[0]
+    X = sim.readback()
+    V = X[0]
+    Xs = X[:, sample] if sample is not None else None
+    del X
     sim.close()
     vsteps = w.n * w.n_steps
     iters = st["newton_iters"] / steps
@@ -223,7 +271,24 @@ def run_pass_set(I, torch, w, steps, warmup, predictor="newton"):
     kavg = float(np.mean(kernel_ms)) / 1e3
     achieved = flops / kavg / 1e12
     bytes_launch = w.n * (2 * state_bytes_per_vertex(w.precision) + 2 * 8)  # state r/w, stim, diff
+    tmin = None
+    if predictor == "newton":
+        split = work_split(vsteps, w.n_nodes, w.n_sweeps, iters, w.precision)
+        tmin = {"W64_per_vertex_step": split["W64"] / vsteps,
+                "W32_per_vertex_step": split["W32"] / vsteps,
+                "Wtr_per_vertex_step": split["Wtr"] / vsteps}
+        if rates:
+            # published vector peaks; no figure is published for the transcendental
+            # unit or the software fp64 exp, so both variants take the measured rate
+            spec = {"P64": 78.6e12, "P32": 157.3e12, "trans32": rates["trans32"],
+                    "exp64": rates["exp64"]}
+            ts, tm = t_min(split, w.precision, spec), t_min(split, w.precision, rates)
+            tmin.update({"t_min_spec_ms": ts * 1e3, "frac_spec": round(ts / kavg, 4),
+                         "t_min_measured_ms": tm * 1e3, "frac_measured": round(tm / kavg, 4)})
     return {
+        "newton_tol": w.newton_tol if w.precision == "fp64" else max(w.newton_tol, 1e-6),
+        "t_min": tmin,
+        "X_sample": Xs,
         "value": vsteps * steps / wall,
         "ms_per_step": wall / steps * 1e3,
         "kernel_ms": float(np.mean(kernel_ms)),
@@ -394,28 +459,142 @@ def run_bidomain(I, torch, w, n_steps=100, rtol=1e-8, max_iter=2000, h=0.01, sig
     }
 
 
-def cpu_baseline(n_vertices=2048, n_steps=120):
-    """The oracle (fp64 numpy, single thread) on a bounded sample of the workload."""
-    from threadpoolctl import threadpool_limits
+def microbench(torch):
+    """Measured rates of the units the step kernels are bound by
+    (libionic_microbench.so; best of three launches each)."""
+    import ctypes
+    path = os.path.join(ROOT, "paper_2510_27447_amd", "_lib", "libionic_microbench.so")
+    if not os.path.exists(path):
+        raise RuntimeError("%s is missing: build it with __graft_entry__.build()" % path)
+    mb = ctypes.CDLL(path)
+    mb.ionic_mb_run.restype = ctypes.c_int
+    mb.ionic_mb_run.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double),
+                                ctypes.c_void_p, ctypes.c_size_t]
+    threads = 1 << 21                       # 8 waves per SIMD on every compute unit
+    copy_threads = 1 << 28                  # 2 GiB read + 2 GiB written
+    buf = torch.empty(2 * copy_threads * 8, dtype=torch.uint8, device="cuda")
+    tests = [("fma64_tflops", 0, threads, 20000, 1e12), ("fma32_tflops", 1, threads, 20000, 1e12),
+             ("v_exp_f32_gops", 2, threads, 8000, 1e9), ("expf_gops", 3, threads, 8000, 1e9),
+             ("exp_f64_gops", 4, threads, 1000, 1e9), ("copy_gbs", 5, copy_threads, 1, 1e9)]
+    out = {}
+    for name, which, n, iters, unit in tests:
+        best = None
+        for _ in range(3):
+            sec, ops = ctypes.c_double(), ctypes.c_double()
+            rc = mb.ionic_mb_run(which, n, iters, ctypes.byref(sec), ctypes.byref(ops),
+                                 buf.data_ptr(), buf.numel())
+            if rc != 0:
+                raise RuntimeError("microbenchmark %s failed: hip error %d" % (name, rc))
+            r = ops.value / sec.value
+            best = r if best is None or r > best else best
+        out[name] = round(best / unit, 2)
+    del buf
+    torch.cuda.synchronize()
+    return out
 
-    from oracle.models import TT06
-    from oracle.sdc import advance
-    from paper_2510_27447_amd import workloads as W
-    w = W.c2_tt06(nx=100, ny=100, nz=100)
-    rng = np.random.Generator(np.random.PCG64(11))
-    idx = np.sort(np.concatenate([rng.choice(np.nonzero(w.i_stim)[0], 4, replace=False),
-                                  rng.choice(w.n, n_vertices - 4, replace=False)]))
+
+def cpu_workers():
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return max(1, min(16, avail))
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_sample(w, per_worker, seed=11):
+    """Vertices of the workload the CPU baseline runs: a few on the stimulated
+    face, the rest uniform."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    n = cpu_workers() * per_worker
+    stim = np.nonzero(w.i_stim)[0]
+    idx = np.concatenate([rng.choice(stim, 16, replace=False),
+                          rng.choice(np.setdiff1d(np.arange(w.n), stim), n - 16, replace=False)])
+    return np.sort(idx)
+
+
+def cpu_baseline(w, idx):
+    """The oracle (fp64 numpy, one thread per worker process, one worker per
+    available core up to 16) on disjoint vertex subsets of the same workload,
+    all 500 steps.  Throughput = sampled vertex-steps / the slowest worker's
+    time.  Also returns the oracle's final states of the sampled vertices."""
+    from oracle.pool import advance_parallel
     s = w.subset(idx)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        advance(TT06, s.x0, dt=s.dt, n_steps=n_steps, n_nodes=s.n_nodes, n_sweeps=s.n_sweeps,
-                i_stim=s.i_stim, stim_on=s.stim_t_on, stim_off=s.stim_t_off, i_diff=s.i_diff,
-                tol=s.newton_tol, maxit=s.newton_maxit)
-        dt = time.perf_counter() - t0
-    return {"value": n_vertices * n_steps / dt, "unit": "vertex-steps/s", "cores": 1,
-            "kind": "oracle",
-            "sample": "%d vertices (4 stimulated) x %d steps of the C2 slab, fp64 numpy oracle, "
-                      "1 thread, %.1f s" % (n_vertices, n_steps, dt)}
+    k = cpu_workers()
+    X, secs, wall = advance_parallel("TT06", s.x0, s.i_stim, s.i_diff, k, dt=s.dt,
+                                     n_steps=s.n_steps, n_nodes=s.n_nodes, n_sweeps=s.n_sweeps,
+                                     stim_on=s.stim_t_on, stim_off=s.stim_t_off,
+                                     tol=s.newton_tol, maxit=s.newton_maxit)
+    slowest = max(secs)
+    vs = len(idx) * s.n_steps
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count()
+    return {"value": vs / slowest, "unit": "vertex-steps/s", "cores": k, "kind": "oracle",
+            "threads_per_process": 1, "nproc": nproc, "os_cpu_count": os.cpu_count(),
+            "cpu_model": cpu_model(),
+            "sample": "%d vertices of the C2/C3 slab (16 on the stimulated face) x %d steps, "
+                      "fp64 numpy oracle, %d processes x 1 thread, slowest %.1f s (wall %.1f s)"
+                      % (len(idx), s.n_steps, k, slowest, wall)}, X
+
+
+def state_errors(Xg, Xo, names):
+    """Max and RMS per state of |GPU - oracle|, relative to the state's max |oracle|."""
+    out = {}
+    for i, nm in enumerate(names):
+        sc = max(float(np.max(np.abs(Xo[i]))), 1e-300)
+        d = np.abs(Xg[i] - Xo[i])
+        out[nm] = {"max": float(np.max(d) / sc), "rms": float(np.sqrt(np.mean(d * d)) / sc)}
+    return out
+
+
+def run_c4(I, torch, precision):
+    """One pass of the 8e6-vertex spiral (1000 steps of dt 0.01 ms, 4 nodes, 3
+    sweeps, the diffusion input redrawn every 50 steps: 20 launches), with all
+    20 input fields resident before the timed region."""
+    from paper_2510_27447_amd import workloads as W
+    w = W.c4_tt06_spiral(precision=precision)
+    sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
+                       newton_maxit=w.newton_maxit)
+    I.ionic_gates_to_steady_state(sim.handle)
+    diffs = [torch.as_tensor(d).cuda() for d in w.i_diff_series]
+    n, n_steps = w.n, w.n_steps
+    del w.x0, w.i_diff_series
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    I.ionic_reset_stats(sim.handle)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    done, k = 0, 0
+    while done < n_steps:
+        chunk = min(w.diff_period, n_steps - done)
+        sim.step(done * w.dt, w.dt, chunk, w.n_nodes, w.n_sweeps, None, 0.0, 0.0, diffs[k],
+                 stream=stream)
+        done += chunk
+        k += 1
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    st = sim.stats()
+    sim.close()
+    del diffs
+    vs = n * n_steps
+    return {"value": vs / wall, "kernel_s": e0.elapsed_time(e1) / 1e3, "wall_s": wall,
+            "launches": k, "newton_iters_per_solve": st["newton_iters"] / max(1, st["newton_solves"]),
+            "n_nonfinite": st["n_nonfinite"], "n_nonconverged": st["n_nonconverged"],
+            "newton_tol": 1e-10 if precision == "fp64" else 1e-6}
 
 
 def main():
@@ -430,6 +609,10 @@ def main():
     ap.add_argument("--no-rl", action="store_true")
     ap.add_argument("--no-diffusion", action="store_true")
     ap.add_argument("--no-bidomain", action="store_true")
+    ap.add_argument("--no-c4", action="store_true")
+    ap.add_argument("--no-micro", action="store_true")
+    ap.add_argument("--cpu-per-worker", type=int, default=256,
+                    help="vertices per CPU worker of the oracle baseline (500 steps each)")
     ap.add_argument("--adaptive-tol", type=float, default=1e-3)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
@@ -449,15 +632,31 @@ def main():
     from paper_2510_27447_amd import workloads as W
 
     I.lib()
+    rates = None
+    micro = None
+    if not args.no_micro:
+        print("[bench] unit-rate microbenchmarks", file=sys.stderr, flush=True)
+        micro = microbench(torch)
+        rates = {"P64": micro["fma64_tflops"] * 1e12, "P32": micro["fma32_tflops"] * 1e12,
+                 "trans32": micro["v_exp_f32_gops"] * 1e9, "exp64": micro["exp_f64_gops"] * 1e9}
+        print("[bench] %s" % micro, file=sys.stderr, flush=True)
+    sample = cpu_sample(W.c2_tt06(), args.cpu_per_worker)
     res = {}
     for prec in ("fp64", "mixed"):
         w = W.c2_tt06(precision=prec)
         print("[bench] %s: %d vertices x %d steps, %d passes" % (w.name, w.n, w.n_steps, args.steps),
               file=sys.stderr, flush=True)
-        res[prec] = run_pass_set(I, torch, w, args.steps, args.warmup)
+        res[prec] = run_pass_set(I, torch, w, args.steps, args.warmup, sample=sample, rates=rates)
         print("[bench] %s: %.3e vertex-steps/s, kernel %.1f ms" % (prec, res[prec]["value"],
               res[prec]["kernel_ms"]), file=sys.stderr, flush=True)
     Vf, Vm = res["fp64"].pop("V"), res["mixed"].pop("V")
+    # like for like: the fp64 kernel at the mixed path's Newton tolerance
+    w = W.c2_tt06(precision="fp64")
+    w.newton_tol = 1e-6
+    print("[bench] fp64 at Newton tol 1e-6", file=sys.stderr, flush=True)
+    f6 = run_pass_set(I, torch, w, args.steps, args.warmup)
+    f6.pop("V")
+    fp64_tol6 = {k: f6[k] for k in ("value", "kernel_ms", "newton_iters_per_solve", "newton_tol")}
 
     def verr(V):
         return {"max": float(np.max(np.abs(V - Vf)) / np.max(np.abs(Vf))),
@@ -516,10 +715,31 @@ def main():
         print("[bench] serving trace: %d requests" % args.serving_requests, file=sys.stderr, flush=True)
         serving = serve.run_trace(W.c5_trace(n_requests=args.serving_requests), verbose=True)
 
+    c4 = None
+    if not args.no_c4:
+        c4 = {}
+        for prec in ("fp64", "mixed"):
+            print("[bench] C4 spiral 8e6 vertices x 1000 steps, %s" % prec, file=sys.stderr,
+                  flush=True)
+            c4[prec] = run_c4(I, torch, prec)
+            print("[bench] C4 %s: %.3e vertex-steps/s" % (prec, c4[prec]["value"]),
+                  file=sys.stderr, flush=True)
+
     cpu = None
+    oracle_errors = None
     if not args.no_cpu:
-        print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
-        cpu = cpu_baseline()
+        print("[bench] cpu baseline: oracle on %d sampled vertices" % len(sample), file=sys.stderr,
+              flush=True)
+        cpu, Xo = cpu_baseline(W.c2_tt06(), sample)
+        from paper_2510_27447_amd.workloads import STATE_NAMES
+        names = STATE_NAMES["TT06"]
+        oracle_errors = {
+            "sample": "the %d vertices of the CPU baseline, after 500 steps" % len(sample),
+            "mixed": state_errors(res["mixed"]["X_sample"], Xo, names),
+            "fp64": state_errors(res["fp64"]["X_sample"], Xo, names),
+        }
+    for prec in ("fp64", "mixed"):
+        res[prec].pop("X_sample")
 
     m = res["mixed"]
     out = {
@@ -537,18 +757,27 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": "TT06-epi 100x100x100 slab (1e6 vertices), 500 steps of dt 0.02 ms per "
-                        "pass, 3 Gauss-Lobatto nodes, 3 SDC sweeps, Newton tol 1e-10; value = "
-                        "mixed precision (fp32 F/J/solve, fp64 V/Ca/Na/K/residual); fp64 alongside",
+                        "pass, 3 Gauss-Lobatto nodes, 3 SDC sweeps, Newton tol 1e-10 requested "
+                        "(the mixed path stops at max(tol, 1e-6)); value = mixed precision (fp32 "
+                        "F/J/solve, fp64 V/Ca/Na/K/residual); fp64 alongside at 1e-10 and 1e-6",
             "n_vertices": 1_000_000, "steps_per_pass": 500, "dt_ms": 0.02, "nodes": 3, "sweeps": 3,
             "seed": 0,
         },
         "kernel_ms": m["kernel_ms"],
+        "newton_tol": m["newton_tol"],
         "fp64": {k: res["fp64"][k] for k in ("value", "ms_per_step", "kernel_ms", "roofline",
-                                            "newton_iters_per_solve", "n_nonconverged")},
+                                            "t_min", "newton_iters_per_solve", "n_nonconverged",
+                                            "newton_tol")},
+        "fp64_at_mixed_tol": fp64_tol6,
         "mixed_speedup_vs_fp64": m["value"] / res["fp64"]["value"],
+        "mixed_speedup_vs_fp64_same_tol": m["value"] / fp64_tol6["value"],
         "mixed_vs_fp64_V_error": mixed_err,
+        "error_vs_oracle": oracle_errors,
         "newton_iters_per_solve": m["newton_iters_per_solve"],
         "roofline": m["roofline"],
+        "t_min": m["t_min"],
+        "microbench": micro,
+        "c4_spiral": c4,
         "traffic_algorithmic_bytes": m["traffic_algorithmic_bytes"],
         "hbm_gbs_algorithmic": m["hbm_gbs_algorithmic"],
         "cpu_baseline": cpu,

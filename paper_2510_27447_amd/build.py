@@ -26,6 +26,10 @@ LIBDIR = os.path.join(PKG, "_lib")
 OBJDIR = os.path.join(LIBDIR, "obj")
 LIBNAME = "libionic_sdc.so"
 LIBPATH = os.path.join(LIBDIR, LIBNAME)
+# rate microbenchmarks of the units the step kernels are bound by (measurement
+# support for bench.py, a library of its own)
+MB_SOURCES = ["microbench.hip"]
+MB_LIBPATH = os.path.join(LIBDIR, "libionic_microbench.so")
 
 STEP_FP64 = ["kernels_%s_fp64%s.hip" % (m, p) for m in ("tt06", "lr91") for p in ("", "_ros2", "_rl")]
 STEP_MIXED = ["kernels_%s_mixed%s.hip" % (m, p) for m in ("tt06", "lr91") for p in ("", "_ros2", "_rl")]
@@ -89,15 +93,16 @@ def build(jobs: int = 8, extra_flags=(), verbose: bool = True) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     extra = list(extra_flags)
     with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
-        objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
-    tmp = LIBPATH + ".tmp"
-    cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH] + objs + ["-o", tmp]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr[-6000:]))
-    os.replace(tmp, LIBPATH)
-    if verbose:
-        print("built", LIBPATH, file=sys.stderr)
+        objs = list(ex.map(lambda s: _compile(s, extra), SOURCES + MB_SOURCES))
+    for path, lib_objs in ((LIBPATH, objs[:len(SOURCES)]), (MB_LIBPATH, objs[len(SOURCES):])):
+        tmp = path + ".tmp"
+        cmd = [_hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH] + lib_objs + ["-o", tmp]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("link failed: %s\n%s" % (" ".join(cmd), r.stderr[-6000:]))
+        os.replace(tmp, path)
+        if verbose:
+            print("built", path, file=sys.stderr)
     return LIBPATH
 
 

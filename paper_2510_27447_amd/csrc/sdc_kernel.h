@@ -299,6 +299,44 @@ IONIC_DEV unsigned long long wave_max_u64(unsigned long long x) {
   return x;
 }
 
+// Register-pressure policies of the step kernel (one vertex per lane, one
+// wavefront per SIMD: 512 registers per lane, beyond which it spills to
+// scratch memory).
+//
+// lds: F(X_n) and the quadrature sums Q_m of a sweep live in LDS, one column
+// per lane (lane-consecutive addresses, free of bank conflicts), instead of
+// registers: 456 B per lane with 3 nodes, 608 B with 4, at most 38.9 KB per
+// single-wave workgroup, so the 4 workgroups of a compute unit fit its 160 KB.
+// Used by the double TT06 kernels with 3 and 4 nodes, which otherwise spill.
+//
+// split_evals: in a sweep, the F-only evaluations at nodes 2..M-1 and the F+J
+// evaluations at the same (not yet updated) points are independent of the
+// solve at node 1, and the F values they share are the same.  Left to itself
+// the optimiser merges them and schedules the evaluations of several nodes
+// together, which keeps two or three model evaluations' intermediates live at
+// once.  With split_evals each evaluation starts from a copy of its point that
+// the optimiser cannot see through and behind a scheduling barrier, so the
+// evaluations run one after another (the F values are computed twice, as the
+// algorithm states).  The double kernels spill 2.6x less with it at 3 nodes
+// and 4.4x less at 4 nodes; the fp32 kernel with 3 nodes fits its registers
+// without it and keeps the shared work.  The fp32 ROS2 kernels do not take
+// it: built with it, the TT06 one with 4 nodes returned NaN for every vertex
+// (the cause was not found; the same source is exact in the other kernels).
+
+template <class Model, class Prec, int M, int Pred>
+struct StepPolicy {
+  static constexpr bool large = Model::N > 8;  // TT06; LR91 fits its registers either way
+  static constexpr bool lds = large && !Prec::mixed && (M == 3 || M == 4);
+  static constexpr bool split_evals =
+      large && (!Prec::mixed || (M >= 4 && Pred != 1 /* ROS2 */));
+};
+
+// An opaque copy: the optimiser cannot relate the result to the argument.
+template <class T, int N>
+IONIC_DEV void opaque(T (&x)[N]) {
+  for (int q = 0; q < N; ++q) asm volatile("" : "+v"(x[q]));
+}
+
 template <class Model, class Prec, int M, int Pred>
 __global__ void __launch_bounds__(kBlock)
     sdc_kernel(const LaunchArgs<typename Model::template Params<typename Prec::TE>> args) {
@@ -346,6 +384,25 @@ __global__ void __launch_bounds__(kBlock)
   Node X[M];
   L::load(X[0], src, sd.stride, vi);
 
+  // F0 = F(X_n) and the quadrature sums Q(m, i) of a sweep, in registers or LDS
+  using Pol = StepPolicy<Model, Prec, M, Pred>;
+  __shared__ TE lds_f0[Pol::lds ? N : 1][kBlock];
+  __shared__ double lds_q[Pol::lds ? (M - 1) * N : 1][kBlock];
+  TE reg_f0[Pol::lds ? 1 : N];
+  double reg_q[Pol::lds ? 1 : (M - 1) * N];
+  auto F0 = [&](int i) -> TE& {
+    if constexpr (Pol::lds)
+      return lds_f0[i][threadIdx.x];
+    else
+      return reg_f0[i];
+  };
+  auto Q = [&](int m, int i) -> double& {
+    if constexpr (Pol::lds)
+      return lds_q[m * N + i][threadIdx.x];
+    else
+      return reg_q[m * N + i];
+  };
+
   unsigned long long it_total = 0;
   unsigned int it_max = 0, nonconv = 0;
   TE err_est = TE(0);  // ROS2: largest scaled embedded error of the launch
@@ -353,11 +410,8 @@ __global__ void __launch_bounds__(kBlock)
   for (int step = 0; step < sd.n_steps; ++step) {
     const double t_mid = t0 + (double(sd.step_offset + step) + 0.5) * dt;
     const TE stim = (sd.t_on <= t_mid && t_mid < sd.t_off) ? stim_amp : TE(0);
-    // F(X_n), needed by the sweeps; every predictor evaluates F there first.  The
-    // Newton predictor takes it from its first iteration through a select, so it
-    // starts defined.
-    TE F0[N];
-    static_for<N>([&](auto I) { F0[I] = TE(0); });
+    // F0 = F(X_n), needed by the sweeps: every predictor evaluates F there first
+    // and writes it before anything reads it
 
     if constexpr (Pred == kPredRos2) {
       // ---- predictor: one ROS2 step on each sub-interval
@@ -370,7 +424,7 @@ __global__ void __launch_bounds__(kBlock)
         SinkElim<Model, TE, decltype(b1), true> s(gt, b1);
         call_rhs_FJ<Model, TE>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
         s.solve(u1);
-        if constexpr (m == 0) static_for<N>([&](auto I) { F0[I] = s.f[I]; });
+        if constexpr (m == 0) static_for<N>([&](auto I) { F0(I) = s.f[I]; });
         static_for<N>([&](auto I) { x2[I] = xe[I] + TE(kRosA21) * u1[I]; });
         eval_F<Model, TE>(p, stim, diff, x2, r2);
         static_for<N>([&](auto I) { r2[I] = gt * r2[I] - TE(2) * u1[I]; });
@@ -403,7 +457,7 @@ __global__ void __launch_bounds__(kBlock)
           L::to_eval(X[m], xe);
           SinkGateStep<Model, TE> s;
           call_rhs_masked<Model, TE, GATES>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
-          if constexpr (m == 0) static_for<N>([&](auto I) { F0[I] = s.f[I]; });
+          if constexpr (m == 0) static_for<N>([&](auto I) { F0(I) = s.f[I]; });
           static_for<N - NC>([&](auto GG) {
             constexpr int g = NC + GG;
             const TE z = dtau[m] * s.d[g];
@@ -467,9 +521,11 @@ __global__ void __launch_bounds__(kBlock)
           };
           eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
           // the first iteration on the first sub-interval evaluates at Y = X_n:
-          // its F is the F(X_n) the sweeps need
-          if constexpr (m == 0)
-            static_for<N>([&](auto I) { F0[I] = pick(pass == 0, f[I], F0[I]); });
+          // its F is the F(X_n) the sweeps need (pass counts the wave's
+          // iterations, so this branch is uniform)
+          if constexpr (m == 0) {
+            if (pass == 0) static_for<N>([&](auto I) { F0(I) = f[I]; });
+          }
           ++pass;
           // every quantity below is computed on all lanes and only chosen per
           // lane, with no conditional evaluation, so no divergent branch forms
@@ -499,30 +555,37 @@ __global__ void __launch_bounds__(kBlock)
     // ---- corrections
     if (sd.n_sweeps > 0) {
       for (int k = 0; k < sd.n_sweeps; ++k) {
-        double Q[M - 1][N];
         static_for<M - 1>([&](auto m) {
-          static_for<N>([&](auto i) { Q[m][i] = Sdt[m][0] * double(F0[i]); });
+          static_for<N>([&](auto i) { Q(m, i) = Sdt[m][0] * double(F0(i)); });
         });
         // F at nodes 2..M-1 (node 1 comes with its Jacobian below)
         static_for<M - 2>([&](auto JJ) {
           constexpr int jn = JJ + 2;
           TE xe[N], fj[N];
           L::to_eval(X[jn], xe);
+          if constexpr (Pol::split_evals) opaque(xe);
           eval_F<Model, TE>(p, stim, diff, xe, fj);
           static_for<M - 1>([&](auto m) {
-            static_for<N>([&](auto i) { Q[m][i] += Sdt[m][jn] * double(fj[i]); });
+            static_for<N>([&](auto i) { Q(m, i) += Sdt[m][jn] * double(fj[i]); });
           });
         });
         static_for<M - 1>([&](auto MM) {
           constexpr int m = MM;
           TE xe[N], f[N], delta[N];
+          if constexpr (Pol::split_evals) __builtin_amdgcn_sched_barrier(0);
           L::to_eval(X[m + 1], xe);
-          // r = X^{k+1}_m - X^k_{m+1} + Q_m in double; at m = 0 the evaluation point is
-          // node 1, whose F enters every Q_m
+          if constexpr (Pol::split_evals) opaque(xe);
+          // r = X^{k+1}_m - X^k_{m+1} + Q_m in double, formed before the evaluation
+          // (Q_m is then dead during it); at m = 0 the evaluation point is node 1,
+          // whose F enters every Q_m
+          double r0[N];
+          static_for<N>([&](auto I) {
+            constexpr int i = I;
+            r0[i] = double(L::template at<i>(X[m])) - double(L::template at<i>(X[m + 1])) + Q(m, i);
+          });
           auto bfn = [&](auto I, TE fi) -> TE {
             constexpr int i = I;
-            double r = double(L::template at<i>(X[m])) - double(L::template at<i>(X[m + 1])) +
-                       Q[m][i];
+            double r = r0[i];
             if constexpr (m == 0) r += Sdt[0][1] * double(fi);
             return TE(r);
           };
@@ -530,7 +593,7 @@ __global__ void __launch_bounds__(kBlock)
           if constexpr (m == 0) {
             static_for<M - 2>([&](auto MM2) {
               constexpr int mm = MM2 + 1;
-              static_for<N>([&](auto i) { Q[mm][i] += Sdt[mm][1] * double(f[i]); });
+              static_for<N>([&](auto i) { Q(mm, i) += Sdt[mm][1] * double(f[i]); });
             });
           }
           static_for<N>([&](auto I) {

@@ -74,3 +74,22 @@ def test_bench_rush_larsen_constants_and_formula():
     for M, K in ((2, 1), (3, 3)):
         assert (b.flops_per_launch_rl(b.TT06_FLOPS, b.TT06_RL_FLOPS, 19, 6, 1000, M, K, 2400)
                 == flops_per_launch_rl(b.TT06_FLOPS, b.TT06_RL_FLOPS, 19, 6, 1000, M, K, 2400))
+
+
+def test_bench_kind_counts_and_split():
+    """The per-kind counts behind the t_min split equal the counter's, and the
+    split of a launch partitions the algorithmic count exactly (every flop is
+    assigned to one unit: W64, W32 or the transcendental unit)."""
+    b = _bench()
+    ev = per_evaluation(TT06, tt06.published_initial(), 6)
+    assert ev["F_detail"] == b.TT06_KINDS["F"]
+    assert ev["FJ_detail"] == b.TT06_KINDS["FJ"]
+    for M, K, it in ((3, 3, 2400), (4, 3, 3100), (2, 1, 1000)):
+        vs = 1000
+        total = b.flops_per_launch(b.TT06_FLOPS, 19, vs, M, K, it)
+        f = b.work_split(vs, M, K, it, "fp64")
+        assert f["W32"] == 0 and f["W64"] + f["Wtr"] == total
+        assert f["Wtr"] == (vs * K * (M - 2) * 57 + (it + vs * K * (M - 1)) * 57)
+        m = b.work_split(vs, M, K, it, "mixed")
+        assert m["W64"] + m["W32"] + m["Wtr"] == total
+        assert m["Wtr"] > f["Wtr"]          # divisions, sqrt and pivot reciprocals join
