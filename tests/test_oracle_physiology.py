@@ -137,6 +137,63 @@ def test_lr91_original_set_action_potential():
     assert 300.0 < apd < 420.0
 
 
+def ap_metrics(model, x0, amp, dur, T, t_fine=10.0):
+    """Action-potential figures of one cell by an independent integrator (scipy
+    BDF with the oracle's exact Jacobian; steps of at most 5 us through the
+    upstroke): resting V, peak V, the largest dV/dt (mV/ms = V/s, the right-hand
+    side itself on a 1 us grid through the upstroke) with its time, and APD90
+    from that time to 90% repolarisation."""
+    def rhs(t, y):
+        s = np.array([amp if t < dur else 0.0])
+        return model.F(y[:, None], s, ZERO)[:, 0]
+
+    def jac(t, y):
+        s = np.array([amp if t < dur else 0.0])
+        return model.FJ(y[:, None], s, ZERO)[1][0]
+
+    kw = dict(method="BDF", jac=jac, rtol=1e-9, atol=1e-11, dense_output=True)
+    legs = [solve_ivp(rhs, (0.0, dur), x0, max_step=0.005, **kw)]
+    legs.append(solve_ivp(rhs, (dur, t_fine), legs[-1].y[:, -1], max_step=0.005, **kw))
+    if T > t_fine:
+        legs.append(solve_ivp(rhs, (t_fine, T), legs[-1].y[:, -1], max_step=1.0, **kw))
+    tf = np.arange(0.0, t_fine, 0.001)
+    Yf = np.concatenate([leg.sol(tf[(tf >= leg.t[0]) & (tf < leg.t[-1])]) for leg in legs[:2]],
+                        axis=1)
+    tf = tf[:Yf.shape[1]]
+    dv = np.array([rhs(t, y)[0] for t, y in zip(tf, Yf.T)])
+    t_up = tf[int(np.argmax(dv))]
+    t = np.concatenate([leg.t for leg in legs])
+    V = np.concatenate([leg.y[0] for leg in legs])
+    peak = max(V.max(), Yf[0].max())
+    v90 = peak - 0.9 * (peak - x0[0])
+    after = (t > t_up) & (t > t[int(np.argmax(V))])
+    k = np.nonzero(after & (V < v90))[0]
+    apd = np.inf
+    if len(k):
+        k = k[0]
+        apd = t[k - 1] + (v90 - V[k - 1]) * (t[k] - t[k - 1]) / (V[k] - V[k - 1]) - t_up
+    return {"rest": x0[0], "peak": peak, "dvdt": dv.max(), "t_up": t_up, "apd90": apd}
+
+
+@pytest.mark.slow
+def test_lr91_original_set_publication_figures():
+    """The publication's conductances reproduce its control action potential:
+    resting potential -84.5 mV, overshoot +59 mV, APD90 364 ms (stimulus -80
+    uA/cm^2 for 1 ms) and a maximal upstroke velocity of 400 V/s.  The overshoot
+    and dV/dt depend on the stimulus while it overlaps the upstroke; dV/dt is
+    taken with a stimulus (-40 for 1 ms) that ends before the upstroke, so that
+    it is the membrane's own.  Tight bands: a one-constant slip in a
+    conductance, a reversal potential or a gate rate moves one of them out."""
+    x = rest.solve_rest(LR91_ORIGINAL, lr91.rest_guess())
+    assert abs(x[0] - (-84.5)) <= 0.5
+    m = ap_metrics(LR91_ORIGINAL, x, -80.0, 1.0, 450.0)
+    assert abs(m["peak"] - 59.0) <= 3.0, m
+    assert abs(m["apd90"] - 364.0) <= 0.05 * 364.0, m
+    u = ap_metrics(LR91_ORIGINAL, x, -40.0, 1.0, 10.0)
+    assert u["t_up"] > 1.0, u                      # the upstroke follows the stimulus
+    assert abs(u["dvdt"] - 400.0) <= 40.0, u
+
+
 @pytest.mark.slow
 def test_tt06_epi_action_potential():
     peak, dvdt, apd = action_potential(TT06, tt06.published_initial(), -52.0, 1.0, 380.0)

@@ -6,7 +6,8 @@ order.  Per vertex (diffusion fixed) the same holds for the M = 2, K = 1
 scheme, and more sweeps/nodes give min(K+1, 2M-2).  Checked on a smooth,
 unstimulated window from a perturbed state, against the oracle itself with
 5 nodes and 8 sweeps (order 8) at a 4x finer step, far more accurate than
-every tested run.
+every tested run.  The settings of the benchmark workloads (3 nodes and 3
+sweeps; 4 nodes and 3 sweeps) are checked for fourth order.
 """
 import numpy as np
 import pytest
@@ -44,6 +45,29 @@ def orders(model, M, K, T=1.0, dts=(0.1, 0.05, 0.025)):
 def test_order_on_cell_models(model, M, K, p):
     o = orders(model, M, K)
     assert o[-1] > p - 0.3
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("model", [LR91, TT06], ids=["LR91", "TT06"])
+@pytest.mark.parametrize("M,K", [(3, 3), (4, 3)], ids=["M3K3", "M4K3"])
+def test_fourth_order_at_the_benchmark_settings(model, M, K):
+    """The slab's setting (3 nodes, 3 sweeps) and the spiral's (4 nodes, 3
+    sweeps) are fourth order: min(K+1, 2M-2) = 4.  The stiff gates keep the
+    coarse steps pre-asymptotic, so the order is the least-squares slope of
+    log|V error| over four halvings from 0.1 ms; a dropped sweep, a wrong
+    quadrature weight or node would leave it at 3 or below."""
+    dts = np.array((0.1, 0.05, 0.025, 0.0125))
+    X0 = perturbed(model)
+    T, dref = 1.0, dts[-1] / 4
+    ref, _ = advance(model, X0, dt=dref, n_steps=int(round(T / dref)), n_nodes=5, n_sweeps=8,
+                     tol=1e-14)
+    errs = []
+    for dt in dts:
+        X, _ = advance(model, X0, dt=dt, n_steps=int(round(T / dt)), n_nodes=M, n_sweeps=K,
+                       tol=1e-14)
+        errs.append(abs(X[0, 0] - ref[0, 0]))
+    slope = np.polyfit(np.log2(dts), np.log2(errs), 1)[0]
+    assert slope > 3.6, (errs, slope)
 
 
 def test_newton_maxit_is_counted_not_raised():
