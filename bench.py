@@ -95,7 +95,8 @@ def traffic_from_counters(fetch_csv, write_csv):
                 # the Newton kernels: predictor 0, the last template argument
                 if not name.split(">")[0].rstrip().endswith("0"):
                     continue
-                kern["fp64" if "Fp64" in name else "mixed"] = v
+                # the first dispatch of each precision: the Newton tol 1e-10 pass
+                kern.setdefault("fp64" if "Fp64" in name else "mixed", v)
             elif "copyBuffer" in name and v > 1e6:
                 copies.append(v)
         # the two largest copy sizes are the fp64 and mixed state restores
@@ -459,6 +460,110 @@ def run_bidomain(I, torch, w, n_steps=100, rtol=1e-8, max_iter=2000, h=0.01, sig
     }
 
 
+def valu_mix(csv_paths, n_steps=500):
+    """Instruction mix of the Newton step kernels from rocprofv3 --pmc runs of
+    `bench.py --steps 1 --warmup 0` (the first dispatch of each precision: the
+    Newton tol 1e-10 pass), per wave and time step, as a markdown table."""
+    counts = {}
+    for path in csv_paths:
+        seen = {}
+        for r in csv.DictReader(open(path)):
+            name = r["Kernel_Name"]
+            if "sdc_kernel" not in name or not name.split(">")[0].rstrip().endswith("0"):
+                continue
+            prec = "fp64" if "Fp64" in name else "mixed"
+            d = seen.setdefault(prec, r["Dispatch_Id"])
+            if r["Dispatch_Id"] != d:
+                continue
+            c = counts.setdefault(prec, {})
+            c[r["Counter_Name"]] = c.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    cols = ["SQ_INSTS_VALU", "SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32",
+            "SQ_INSTS_VALU_FMA_F32", "SQ_INSTS_VALU_TRANS_F32", "SQ_INSTS_VALU_ADD_F64",
+            "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_TRANS_F64",
+            "SQ_INSTS_VALU_CVT", "SQ_INSTS_VALU_INT32", "SQ_INSTS_VALU_INT64", "SQ_INSTS_SALU",
+            "SQ_INSTS_LDS", "SQ_INSTS_VMEM"]
+    lines = ["| counter (per wave and step) | " + " | ".join(sorted(counts)) + " |",
+             "|---|" + "---|" * len(counts)]
+    for col in cols + ["other VALU"]:
+        vals = []
+        for prec in sorted(counts):
+            c = counts[prec]
+            waves = c.get("SQ_WAVES", 15625.0)
+            if col == "other VALU":
+                typed = sum(c.get(k, 0.0) for k in cols[1:12])
+                v = c.get("SQ_INSTS_VALU", 0.0) - typed
+            else:
+                v = c.get(col, float("nan"))
+            vals.append("%.0f" % (v / waves / n_steps))
+        lines.append("| %s | %s |" % (col.replace("SQ_INSTS_", ""), " | ".join(vals)))
+    for prec in sorted(counts):
+        c = counts[prec]
+        if "SQ_ACTIVE_INST_VALU" in c and "SQ_BUSY_CYCLES" in c:
+            lines.append("")
+            # SQ_ACTIVE_INST_VALU counts quad-cycles
+            lines.append("%s: 4 SQ_ACTIVE_INST_VALU / SQ_INSTS_VALU = %.2f cycles per wave64 VALU "
+                         "instruction" % (prec, 4 * c["SQ_ACTIVE_INST_VALU"] / c["SQ_INSTS_VALU"]))
+    print("\n".join(lines))
+    return counts
+
+
+def trace_overlap(trace_csv, skip=0):
+    """Concurrency of the step kernels of different classes (cell model x
+    precision) in a rocprofv3 kernel trace (--kernel-trace, CSV): the time
+    during which at least one step kernel runs, the time during which kernels
+    of two or more classes run at once, and the same per class pair.  The
+    first `skip` step-kernel dispatches (in start order) are left out."""
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    iv = []
+    for r in rows:
+        name = r.get("Kernel_Name", "")
+        if "sdc_kernel" not in name:
+            continue
+        if skip > 0:
+            skip -= 1
+            continue
+        cls = ("TT06" if "TT06" in name else "LR91" if "LR91" in name else "test",
+               "fp64" if "Fp64" in name else "mixed")
+        iv.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), cls,
+                   r.get("Queue_Id", r.get("Stream_Id", "?"))))
+    events = sorted([(a, 1, c) for a, b, c, q in iv] + [(b, -1, c) for a, b, c, q in iv])
+    running = {}
+    busy = multi = 0
+    pair = {}
+    last = None
+    for t, d, c in events:
+        if last is not None and running:
+            dt = t - last
+            live = [k for k, v in running.items() if v > 0]
+            if live:
+                busy += dt
+            if len(live) >= 2:
+                multi += dt
+                key = " + ".join("%s/%s" % k for k in sorted(live))
+                pair[key] = pair.get(key, 0) + dt
+        running[c] = running.get(c, 0) + d
+        if running[c] == 0:
+            del running[c]
+        last = t
+    per_class = {}
+    for a, b, c, q in iv:
+        k = "%s/%s" % c
+        per_class.setdefault(k, [0, 0.0, set()])
+        per_class[k][0] += 1
+        per_class[k][1] += (b - a) * 1e-9
+        per_class[k][2].add(q)
+    out = {"step_kernel_dispatches": len(iv), "busy_s": busy * 1e-9,
+           "two_or_more_classes_s": multi * 1e-9,
+           "overlap_fraction_of_busy": multi / busy if busy else 0.0,
+           "kernel_time_sum_s": sum((b - a) for a, b, c, q in iv) * 1e-9,
+           "per_class": {k: {"dispatches": v[0], "kernel_s": round(v[1], 4),
+                             "queues": sorted(v[2])} for k, v in sorted(per_class.items())},
+           "concurrent_sets_s": {k: round(v * 1e-9, 4) for k, v in
+                                 sorted(pair.items(), key=lambda kv: -kv[1])[:8]}}
+    print(json.dumps(out, indent=1))
+    return out
+
+
 def microbench(torch):
     """Measured rates of the units the step kernels are bound by
     (libionic_microbench.so; best of three launches each)."""
@@ -616,9 +721,23 @@ def main():
     ap.add_argument("--adaptive-tol", type=float, default=1e-3)
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write the traffic summary from two rocprofv3 --pmc runs and exit")
+    ap.add_argument("--trace-overlap", metavar="KERNEL_TRACE_CSV",
+                    help="print the class overlap of the step kernels in a rocprofv3 kernel "
+                         "trace and exit")
+    ap.add_argument("--valu-from", nargs="+", metavar="PMC_CSV",
+                    help="print the instruction mix of the step kernels from rocprofv3 --pmc "
+                         "runs and exit")
+    ap.add_argument("--trace-skip", type=int, default=0,
+                    help="with --trace-overlap: leave out the first N step-kernel dispatches")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic_file(*args.traffic_from)
+        return
+    if args.valu_from:
+        valu_mix(args.valu_from)
+        return
+    if args.trace_overlap:
+        trace_overlap(args.trace_overlap, args.trace_skip)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the reaction stage shards by vertex ranges with no "

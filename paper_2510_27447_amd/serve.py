@@ -7,10 +7,10 @@ class (cell model x precision x node count, the unit one kernel instantiation
 serves) together: each round launches one batched kernel per class over a
 chunk of steps (reaction_sdc_step_batch), on one stream per class so the
 classes overlap on the GPU.  Between chunks it retires finished requests
-(their final V is read back) and admits arrivals in FIFO order while the
-resident footprint stays within the HBM budget and a slot is free.  A request
-computes exactly what it computes alone: every vertex's arithmetic is
-independent of what else shares the launch.
+(their final V is copied to the host) and admits arrivals in FIFO order while
+the resident footprint stays within the HBM budget and a slot is free; neither
+step waits for the device.  A request computes exactly what it computes alone:
+every vertex's arithmetic is independent of what else shares the launch.
 
 Latency of a request = time its result (final V on the host) is ready minus
 its arrival time.  Throughput = total vertex-steps / (last completion - first
@@ -69,14 +69,16 @@ class Admission:
 @dataclass
 class _Job:
     req: object
-    wl: object
     sim: object
-    stim: object
-    diff: object
+    inputs: tuple          # device tensors kept alive while the job runs
     footprint: float
     remaining: int
     t_admit: float
-    result: Optional[np.ndarray] = None
+    ready: object          # event on the upload stream: state and inputs in place
+    waited: bool = False   # the class stream has been made to wait for `ready`
+    host_v: object = None  # pinned host copy of V once the job has finished
+    copied: object = None  # event: host_v is complete
+    state: Optional[np.ndarray] = None
 
 
 @dataclass
@@ -105,10 +107,22 @@ class Server:
     keep_state: bool = False            # keep each result's full state (tests)
     results: List[Result] = field(default_factory=list)
     rejected: List[int] = field(default_factory=list)
+    trace_log: List[tuple] = field(default_factory=list)  # (class, t_launch) per batched launch
 
     def run(self, trace, verbose=False, time_scale=1.0):
         """Serve the requests of `trace` (arrival times in seconds, replayed in
-        wall-clock time divided by time_scale).  Returns the list of Results."""
+        wall-clock time divided by time_scale).  Returns the list of Results.
+
+        Nothing on the admit or retire path waits for the device: a request's
+        state and inputs are built on the GPU on an upload stream (the initial
+        state shared by every vertex is broadcast there, the diffusion current
+        travels from pinned host memory) and its class stream waits for that
+        upload by an event; a finished request's V (plane 0 of the state, double
+        in both precision layouts) is copied to pinned host memory
+        asynchronously, and the request completes once that copy's event has
+        fired.  Its handle is closed, and its memory and slot released, at the
+        next point where its class stream has no chunk in flight (closing waits
+        for the streams the handle has used).""" 
         import torch
 
         from . import ionic as I
@@ -117,6 +131,8 @@ class Server:
         streams: Dict[tuple, "torch.cuda.Stream"] = {}
         upload = torch.cuda.Stream()
         active: Dict[tuple, List[_Job]] = {}
+        retiring: List[tuple] = []
+        closing: List[tuple] = []
         inflight: Dict[tuple, "torch.cuda.Event"] = {}
         pending = deque(sorted(trace, key=lambda r: r.arrival))
         waiting: deque = deque()
@@ -126,35 +142,56 @@ class Server:
             return (time.perf_counter() - t0) * time_scale
 
         def start(req):
-            w = req.materialize()
+            x0c, amp, n_stim, (t_on, t_off), diff_np = req.compact_inputs()
+            n = req.n
             with torch.cuda.stream(upload):
-                sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
-                                   newton_maxit=w.newton_maxit, stream=upload)
-                stim = torch.as_tensor(w.i_stim).to("cuda", non_blocking=False)
-                diff = torch.as_tensor(w.i_diff).to("cuda", non_blocking=False)
-            upload.synchronize()
-            I.ionic_set_inputs(sim.handle, 0.0, w.dt, w.n_nodes, w.n_sweeps, stim, w.stim_t_on,
-                               w.stim_t_off, diff)
-            return _Job(req, w, sim, stim, diff, req.footprint_bytes(), w.n_steps, now())
+                x0 = torch.as_tensor(x0c).to("cuda", non_blocking=True)[:, None].expand(-1, n)
+                x0 = x0.contiguous()
+                stim = torch.zeros(n, dtype=torch.float64, device="cuda")
+                stim[:n_stim] = amp
+                diff = torch.from_numpy(diff_np).pin_memory().to("cuda", non_blocking=True)
+                sim = I.Simulation(req.model, x0, precision=req.precision, stream=upload)
+                ready = torch.cuda.Event()
+                ready.record(upload)
+            I.ionic_set_inputs(sim.handle, 0.0, req.dt, req.n_nodes, req.n_sweeps, stim, t_on,
+                               t_off, diff)
+            return _Job(req, sim, (x0, stim, diff), req.footprint_bytes(), req.n_steps, now(),
+                        ready)
 
-        def finish(cls, job):
+        def begin_finish(cls, job):
+            """Enqueue the copy of the result; the class stream is idle here."""
             st = streams[cls]
-            with torch.cuda.stream(st):
-                if self.keep_state:
-                    state = job.sim.readback(stream=st)
-                    V = state[0].copy()
+            n = job.sim.n
+            if not job.waited:           # a request with no steps: its upload still orders
+                st.wait_event(job.ready)
+                job.waited = True
+            if self.keep_state:
+                ns = job.sim.n_states
+                if ns * n * 8 <= (8 << 20):   # through the library's static staging buffer
+                    job.state = I.state_readback_noalloc(job.sim.handle, ns, 0, n, stream=st)
                 else:
-                    out = torch.empty((job.sim.n_states, job.sim.n), dtype=torch.float64, device="cuda")
-                    I.state_readback(job.sim.handle, job.sim.n_states, 0, job.sim.n, out=out, stream=st)
-                    V = out[0].cpu().numpy()
-                    state = None
+                    job.state = job.sim.readback(stream=st)
+            with torch.cuda.stream(st):
+                v_dev = job.sim.state[: n * 8].view(torch.float64)
+                job.host_v = torch.empty(n, dtype=torch.float64, pin_memory=True)
+                job.host_v.copy_(v_dev, non_blocking=True)
+                job.copied = torch.cuda.Event()
+                job.copied.record(st)
+            retiring.append((cls, job))
+
+        def complete(cls, job):
             r = job.req
             self.results.append(Result(r.rid, r.model, r.precision, r.n, r.n_steps, r.arrival,
-                                       job.t_admit, now(), V, state))
+                                       job.t_admit, now(), job.host_v.numpy().copy(), job.state))
+            closing.append((cls, job))
+
+        def close(job):
             job.sim.close()
+            job.sim.state = None
+            job.inputs = None
             policy.release(job.footprint)
 
-        while pending or waiting or any(active.values()):
+        while pending or waiting or any(active.values()) or retiring or closing:
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
@@ -164,12 +201,24 @@ class Server:
                 if inflight[cls].query():
                     del inflight[cls]
                     progressed = True
-            # retire finished jobs of idle classes
+            # results that reached the host
+            for item in list(retiring):
+                if item[1].copied.query():
+                    retiring.remove(item)
+                    complete(*item)
+                    progressed = True
+            # handles of completed requests whose class has nothing in flight
+            for item in list(closing):
+                if item[0] not in inflight:
+                    closing.remove(item)
+                    close(item[1])
+                    progressed = True
+            # finished jobs of idle classes start their result copy
             for cls, jobs in active.items():
                 if cls in inflight:
                     continue
                 for job in [j for j in jobs if j.remaining == 0]:
-                    finish(cls, job)
+                    begin_finish(cls, job)
                     jobs.remove(job)
                     progressed = True
             # admit arrivals
@@ -189,17 +238,22 @@ class Server:
             for cls, jobs in active.items():
                 if cls in inflight or not jobs:
                     continue
-                steps = [min(self.chunk_steps, j.remaining) for j in jobs]
                 st = streams[cls]
+                for j in jobs:
+                    if not j.waited:
+                        st.wait_event(j.ready)
+                        j.waited = True
+                steps = [min(self.chunk_steps, j.remaining) for j in jobs]
                 I.reaction_sdc_step_batch([j.sim.handle for j in jobs], steps, stream=st)
                 ev = torch.cuda.Event()
                 ev.record(st)
                 inflight[cls] = ev
+                self.trace_log.append((cls, now()))
                 for j, k in zip(jobs, steps):
                     j.remaining -= k
                 progressed = True
             if not progressed:
-                time.sleep(0.0005)
+                time.sleep(0.0002)
         torch.cuda.synchronize()
         return self.results
 

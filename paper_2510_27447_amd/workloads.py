@@ -162,14 +162,22 @@ class Request:
         per = n_states * 8 if self.precision == "fp64" else n_fp64 * 8 + (n_states - n_fp64) * 4
         return stride * per + 2 * 8 * self.n          # state + stimulus + diffusion input
 
-    def materialize(self) -> Workload:
+    def compact_inputs(self):
+        """The request's inputs in compact form: the initial state shared by every
+        vertex (n_states,), the stimulus amplitude and the number of stimulated
+        leading vertices, the stimulus window, and the diffusion current (n,)."""
         rng = np.random.Generator(np.random.PCG64(self.seed))
-        x0 = np.tile(initial_state(self.model)[:, None], (1, self.n))
-        stim = np.zeros(self.n)
-        stim[: max(1, self.n // 10)] = -80.0 if self.model == "LR91" else -100.0
+        amp = -80.0 if self.model == "LR91" else -100.0
         diff = rng.normal(0.0, 0.5, self.n)
+        return initial_state(self.model), amp, max(1, self.n // 10), (0.0, 1.0), diff
+
+    def materialize(self) -> Workload:
+        x0c, amp, n_stim, (t_on, t_off), diff = self.compact_inputs()
+        x0 = np.tile(x0c[:, None], (1, self.n))
+        stim = np.zeros(self.n)
+        stim[:n_stim] = amp
         return Workload("C5-req%d" % self.rid, self.model, self.precision, x0, self.dt,
-                        self.n_steps, self.n_nodes, self.n_sweeps, 1e-10, 10, stim, 0.0, 1.0,
+                        self.n_steps, self.n_nodes, self.n_sweeps, 1e-10, 10, stim, t_on, t_off,
                         diff, seed=self.seed)
 
 
