@@ -140,6 +140,19 @@ typedef struct {
   int32_t reserved;
 } ionic_elliptic_info;
 
+/* Outcome of reaction_bidomain_implicit_step (sums over the steps of the call). */
+typedef struct {
+  int64_t steps;              /* time steps taken                                       */
+  int64_t inner_passes;       /* passes of Algorithm 2's inner loop, summed               */
+  int64_t cg_iterations;      /* elliptic CG iterations, summed                          */
+  int64_t krylov_iterations;  /* BiCGSTAB iterations of the stage and correction systems */
+  double last_change;         /* scaled change of the last pass of the last step          */
+  int32_t inner_max;          /* most passes in one step                                 */
+  int32_t converged;          /* 1 iff every step met inner_tol within max_inner          */
+  int32_t krylov_max;         /* most BiCGSTAB iterations of one solve                   */
+  int32_t krylov_converged;   /* 1 iff every BiCGSTAB solve met krylov_rtol              */
+} ionic_implicit_info;
+
 /* Outcome of reaction_sdc_adaptive. */
 typedef struct {
   double t;            /* time reached (ms); equals t_end when reached == 1       */
@@ -338,6 +351,44 @@ int reaction_bidomain_step(ionic_sim* sim, const ionic_bidomain_grid* grid, doub
                            double stim_t_on, double stim_t_off, double* u_dev, void* work_dev,
                            size_t work_bytes, double rtol, int max_iter, double* i_diff_work_dev,
                            ionic_elliptic_info* info, void* hip_stream);
+
+/* Device bytes of the work buffer of reaction_bidomain_implicit_step for this
+ * model, grid and iteration cap (0 on bad arguments). */
+size_t ionic_implicit_work_bytes(int model, int64_t nx, int64_t ny, int64_t nz, int max_iter);
+
+/* Partitioned bidomain stepping as the paper states Algorithm 2 (section
+ * 3.3.2, the partitioned strategy with SDC), the parabolic term implicit: per
+ * time step t^n -> t^n + dt from (X^n, u^n), passes k = 0, 1, ... of
+ *   1. u^{k+1} from A_ie u = -A_i v^k (as ionic_elliptic_solve; v^0 = v^n);
+ *   2. one ROS2 step (section 3.3.1, equation rb_system) from X^n of
+ *      dX/dt = G(X; u^{k+1}), G the cell right-hand side with the current
+ *      -M_L^{-1} A_i (v + u) in the voltage equation, whose Jacobian keeps
+ *      -M_L^{-1} A_i v: both stages solve (I - gamma dt J_G(X^n)) k = ...;
+ *   3. the correction of equation sdc: (I - dt J_G(X~)) eps =
+ *      X^n - X~ + dt/2 (G(X^n; u^n) + G(X~; u^{k+1})), X^{k+1} = X~ + eps;
+ *   4. stop once max_i |X^{k+1}_i - X^k_i| / max(|X^{k+1}_i|, s_i) <= inner_tol
+ *      (s_i the Newton scale of each state) or after max_inner passes;
+ * then X^{n+1} = X^{k+1}, u^{n+1} = u^{k+1}.  Each stage or correction system
+ * couples the vertices through the v block only: every vertex's block is
+ * eliminated onto V by the static sparse elimination, the remaining system
+ * (S + c M_L^{-1} A_i) dv = r over the grid is solved by BiCGSTAB (the
+ * paper's Krylov method) preconditioned by its diagonal to ||r|| <=
+ * krylov_rtol ||r_0||, and each vertex's states follow from dv.  Any step
+ * size is stable (dt = 0.05 ms at h = 0.01 cm, the paper's largest step, is
+ * beyond reaction_bidomain_step's explicit limit).
+ *  u_dev: N doubles, device: u^0 on entry (e.g. from ionic_elliptic_solve),
+ *         the u of the last step on return.
+ *  work_dev: ionic_implicit_work_bytes(model, nx, ny, nz, max_iter) bytes.
+ *  max_iter: cap of every CG and BiCGSTAB solve (not an error when reached:
+ *         info reports it).  IONIC_FP64 handles only (else
+ *         IONIC_EUNSUPPORTED).  Synchronises hip_stream (the host reads each
+ *         pass's change). */
+int reaction_bidomain_implicit_step(ionic_sim* sim, const ionic_bidomain_grid* grid, double t0,
+                                    double dt, int n_steps, const double* i_stim_dev,
+                                    double stim_t_on, double stim_t_off, double* u_dev,
+                                    void* work_dev, size_t work_bytes, double elliptic_rtol,
+                                    double krylov_rtol, double inner_tol, int max_inner,
+                                    int max_iter, ionic_implicit_info* info, void* hip_stream);
 
 /* Store the step inputs of `sim` for reaction_sdc_step_batch (same meaning as
  * the arguments of reaction_sdc_step).  The batch advances the handle's own

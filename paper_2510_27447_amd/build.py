@@ -36,6 +36,7 @@ STEP_MIXED = ["kernels_%s_mixed%s.hip" % (m, p) for m in ("tt06", "lr91") for p 
 # slowest first, so the parallel build ends sooner
 SOURCES = STEP_FP64 + STEP_MIXED + ["kernels_tt06.hip", "kernels_lr91.hip", "kernels_test.hip",
                                     "control.hip", "diffusion.hip", "elliptic.hip", "multigrid.hip",
+                                    "implicit.hip",
                                     "multigrid_plan.cpp",
                                     "ionic.cpp"]
 # per-source optimisation level (default -O3)
@@ -48,7 +49,7 @@ EXTRA = {s: ["-fassociative-math", "-fno-signed-zeros", "-fno-trapping-math"] fo
 # fp64); the scheduler's own register-pressure trackers place fewer spill and
 # register-copy instructions there (the same results bit for bit; TT06 fp64
 # pass 1.58 -> 1.47 s, mixed 243 -> 240 ms on the 1e6-vertex slab)
-for _s in STEP_FP64 + STEP_MIXED:
+for _s in STEP_FP64 + STEP_MIXED + ["implicit.hip"]:
     EXTRA[_s] = EXTRA.get(_s, []) + ["-mllvm", "-amdgpu-use-amdgpu-trackers"]
 ARCH = os.environ.get("IONIC_OFFLOAD_ARCH", "gfx950")
 FLAGS = [

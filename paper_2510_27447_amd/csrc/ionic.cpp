@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "grid_ops.h"
+#include "implicit_ops.h"
 #include "ionic_sdc.h"
 #include "kernel_ops.h"
 
@@ -619,10 +620,11 @@ static int prepare_preconditioner(ionic_sim* s, const ionic::CgParams& c, void* 
 // end is only enqueued.
 static int elliptic_solve_impl(ionic_sim* s, const ionic::CgParams& c, double* u, void* work,
                                double rtol, int max_iter, const Preconditioner& pc,
-                               ionic_elliptic_info* info, hipStream_t st, long long expect = 0) {
+                               ionic_elliptic_info* info, hipStream_t st, long long expect = 0,
+                               const double* V = nullptr) {
   const long long n = s->n;
   ionic::CgWork w = carve_cg_work(work, n, c.nb);
-  const double* V = static_cast<const double*>(s->state);
+  if (!V) V = static_cast<const double*>(s->state);
   const bool jacobi = !pc.mg;
   // z = M^-1 r and its r.z parts when multigrid preconditions; with iter >= 0
   // the cycle first tests ||r_iter|| (xtmp and ytmp are dead vectors of the CG
@@ -770,6 +772,221 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
     if (e != hipSuccess) return hip_fail(e, "launch sdc_kernel (bidomain)");
   }
   IONIC_HIP(hipStreamSynchronize(st));
+  if (info) *info = acc;
+  return IONIC_OK;
+}
+
+// ---- partitioned stepping with the parabolic term implicit ------------------------------
+
+namespace {
+
+// Layout of the work buffer of reaction_bidomain_implicit_step: the elliptic
+// solve's work, six state-sized vectors (n_states planes of stride doubles),
+// five fields of stride doubles, the BiCGSTAB work and one change slot.
+struct ImpWork {
+  void* elliptic;
+  double *XK, *K1, *K2, *XT, *FN, *B;  // state-sized
+  double *idiff, *idiff2, *S, *r, *uK;  // fields
+  ionic::BiCgWork bw;
+  unsigned long long* change;
+};
+
+size_t imp_bytes(int n_states, long long nx, long long ny, long long nz, int max_iter) {
+  const long long n = nx * ny * nz, stride = stride_of(n);
+  const ionic::CgParams c = ionic::cg_params(nx, ny, nz);
+  const size_t ell = (elliptic_bytes(nx, ny, nz, max_iter) + 255) / 256 * 256;
+  return ell + sizeof(double) * size_t(6 * n_states * stride + 5 * stride) +
+         ionic::BiCgWork::bytes(n, c.nb, max_iter) + 256;
+}
+
+ImpWork carve_imp(void* work, int n_states, long long nx, long long ny, long long nz,
+                  int max_iter) {
+  const long long n = nx * ny * nz, stride = stride_of(n);
+  const ionic::CgParams c = ionic::cg_params(nx, ny, nz);
+  ImpWork w;
+  w.elliptic = work;
+  const size_t ell = (elliptic_bytes(nx, ny, nz, max_iter) + 255) / 256 * 256;
+  double* q = reinterpret_cast<double*>(static_cast<char*>(work) + ell);
+  double** state_vecs[6] = {&w.XK, &w.K1, &w.K2, &w.XT, &w.FN, &w.B};
+  for (double** v : state_vecs) {
+    *v = q;
+    q += size_t(n_states) * size_t(stride);
+  }
+  double** fields[5] = {&w.idiff, &w.idiff2, &w.S, &w.r, &w.uK};
+  for (double** v : fields) {
+    *v = q;
+    q += stride;
+  }
+  double** bv[10] = {&w.bw.x, &w.bw.r, &w.bw.rh, &w.bw.p, &w.bw.ph,
+                     &w.bw.v, &w.bw.s, &w.bw.sh, &w.bw.t, &w.bw.dinv};
+  for (double** v : bv) {
+    *v = q;
+    q += n;
+  }
+  for (int a = 0; a < 5; ++a) {
+    w.bw.part[a] = q;
+    q += c.nb;
+  }
+  w.bw.sc = q;
+  q += 8 + 4 * (max_iter + 2);
+  w.change = reinterpret_cast<unsigned long long*>(q);
+  return w;
+}
+
+// One BiCGSTAB solve of (S + cst M_L^{-1} A_i) x = r into w.bw.x; iterations
+// in batches with one synchronisation each.  Adds to the counters of info.
+int bicg_solve(const ionic::CgParams& c, double h, double cst, ImpWork& w, int max_iter,
+               ionic_implicit_info* acc, hipStream_t st) {
+  IONIC_HIP(ionic::bicg_start(c, h, cst, w.S, w.r, w.bw, st));
+  constexpr int kBatch = 4;
+  int k = 0;
+  ionic::BiCgCtl ctl{0, 0, 0};
+  for (;;) {
+    const int until = std::min(max_iter + 1, k + kBatch);
+    for (; k < until; ++k) IONIC_HIP(ionic::bicg_iteration(c, h, cst, w.S, k, w.bw, st));
+    IONIC_HIP(hipMemcpyAsync(&ctl, w.bw.sc + 4, sizeof(ctl), hipMemcpyDeviceToHost, st));
+    IONIC_HIP(hipStreamSynchronize(st));
+    if (ctl.done || k > max_iter) break;
+  }
+  const long long iters = ctl.done ? ctl.iters : max_iter;
+  acc->krylov_iterations += iters;
+  acc->krylov_max = std::max<int32_t>(acc->krylov_max, int32_t(iters));
+  if (!ctl.done) acc->krylov_converged = 0;
+  return IONIC_OK;
+}
+
+}  // namespace
+
+size_t ionic_implicit_work_bytes(int model, int64_t nx, int64_t ny, int64_t nz, int max_iter) {
+  const ModelOps* o = ops_for(model);
+  if (!o || nx < 1 || ny < 1 || nz < 1 || max_iter < 1 || max_iter > (1 << 20)) return 0;
+  if ((__int128)nx * ny * nz >= ((__int128)1 << 31)) return 0;
+  return imp_bytes(o->n_states, nx, ny, nz, max_iter);
+}
+
+int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0,
+                                    double dt, int n_steps, const double* i_stim_dev,
+                                    double stim_t_on, double stim_t_off, double* u_dev,
+                                    void* work_dev, size_t work_bytes, double elliptic_rtol,
+                                    double krylov_rtol, double inner_tol, int max_inner,
+                                    int max_iter, ionic_implicit_info* info, void* hip_stream) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  int rc = check_bidomain_grid(s, g);
+  if (rc != IONIC_OK) return rc;
+  rc = check_step_args(t0, dt, n_steps, 2, 1, stim_t_on, stim_t_off);
+  if (rc != IONIC_OK) return rc;
+  if (s->precision != IONIC_FP64)
+    return fail(IONIC_EUNSUPPORTED, "the implicit partitioned step is built for IONIC_FP64");
+  if (!u_dev || !work_dev) return fail(IONIC_EINVAL, "u_dev or work_dev is NULL");
+  if (!(elliptic_rtol >= 0.0) || !std::isfinite(elliptic_rtol) || !(krylov_rtol >= 0.0) ||
+      !std::isfinite(krylov_rtol) || !(inner_tol >= 0.0) || !std::isfinite(inner_tol))
+    return fail(IONIC_EINVAL, "tolerances must be finite and >= 0");
+  if (max_inner < 1 || max_inner > 1000) return fail(IONIC_EINVAL, "max_inner must be in [1, 1000]");
+  if (max_iter < 1 || max_iter > (1 << 20)) return fail(IONIC_EINVAL, "max_iter out of range");
+  const int ns = s->ops->n_states;
+  const size_t need = imp_bytes(ns, g->nx, g->ny, g->nz, max_iter);
+  if (work_bytes < need)
+    return fail(IONIC_EINVAL, "implicit work buffer too small: need " + std::to_string(need) +
+                                  " bytes");
+  hipStream_t st = static_cast<hipStream_t>(hip_stream);
+  touch(s, st);
+  ionic::CgParams ce = cg_params_of(g, elliptic_rtol);
+  ionic::CgParams ck = cg_params_of(g, krylov_rtol);
+  ImpWork w = carve_imp(work_dev, ns, g->nx, g->ny, g->nz, max_iter);
+  Preconditioner pc;
+  rc = prepare_preconditioner(s, ce, w.elliptic, max_iter, pc, st);
+  if (rc != IONIC_OK) return rc;
+
+  const long long n = s->n, stride = s->stride;
+  const long long elems = (long long)ns * stride;
+  const size_t state_bytes = sizeof(double) * size_t(elems);
+  double* Xn = static_cast<double*>(s->state);
+  const int model = s->model;
+  const void* p64 = s->p64;
+  constexpr double kG = ionic::kRosGamma;
+  ionic_implicit_info acc{};
+  acc.converged = 1;
+  acc.krylov_converged = 1;
+  ionic_elliptic_info ell{0, 0.0, 1, 0};
+
+  // one stage or correction system: reduce at X, BiCGSTAB, expand into out
+  auto stage = [&](const double* X, double c, double cf, const double* base, const double* idiff,
+                   int stim_on, double* out) -> int {
+    ionic::ImpBlock b{};
+    b.X = X;
+    b.n = n;
+    b.stride = stride;
+    b.stim = i_stim_dev;
+    b.stim_on = stim_on;
+    b.idiff = idiff;
+    b.c = c;
+    b.cf = cf;
+    b.base = base;
+    b.expand = 0;
+    b.S = w.S;
+    b.r = w.r;
+    IONIC_HIP(ionic::imp_block(model, p64, b, st));
+    int rc2 = bicg_solve(ck, g->h, c, w, max_iter, &acc, st);
+    if (rc2 != IONIC_OK) return rc2;
+    b.expand = 1;
+    b.dv = w.bw.x;
+    b.out = out;
+    IONIC_HIP(ionic::imp_block(model, p64, b, st));
+    return IONIC_OK;
+  };
+
+  for (int step = 0; step < n_steps; ++step) {
+    const double t_mid = t0 + (double(step) + 0.5) * dt;
+    const int on = (stim_t_on <= t_mid && t_mid < stim_t_off) ? 1 : 0;
+    // G(X^n; u^n) for the correction
+    IONIC_HIP(ionic::bidomain_current(ce, Xn, u_dev, g->h, w.idiff, st));
+    IONIC_HIP(ionic::imp_rhs(model, p64, Xn, n, stride, i_stim_dev, on, w.idiff, 1.0, 0.0, nullptr,
+                             w.FN, st));
+    IONIC_HIP(hipMemcpyAsync(w.XK, Xn, state_bytes, hipMemcpyDeviceToDevice, st));
+    IONIC_HIP(hipMemcpyAsync(w.uK, u_dev, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, st));
+    int passes = 0;
+    double change = 0.0;
+    for (int k = 0; k < max_inner; ++k) {
+      ++passes;
+      // 1. u^{k+1} from v^k
+      rc = elliptic_solve_impl(s, ce, w.uK, w.elliptic, elliptic_rtol, max_iter, pc, &ell, st, 0,
+                               w.XK);
+      if (rc != IONIC_OK) return rc;
+      // 2. ROS2 from X^n with u^{k+1}, both stages on I - gamma tau J(X^n)
+      IONIC_HIP(ionic::bidomain_current(ce, Xn, w.uK, g->h, w.idiff, st));
+      rc = stage(Xn, kG * dt, kG * dt, nullptr, w.idiff, on, w.K1);
+      if (rc != IONIC_OK) return rc;
+      IONIC_HIP(ionic::soa_lincomb(w.XT, Xn, ionic::kRosA21, w.K1, 0.0, nullptr, elems, st));
+      IONIC_HIP(ionic::bidomain_current(ce, w.XT, w.uK, g->h, w.idiff2, st));
+      IONIC_HIP(ionic::imp_rhs(model, p64, w.XT, n, stride, i_stim_dev, on, w.idiff2, kG * dt,
+                               -2.0, w.K1, w.B, st));
+      rc = stage(Xn, kG * dt, 0.0, w.B, w.idiff, on, w.K2);
+      if (rc != IONIC_OK) return rc;
+      IONIC_HIP(ionic::soa_lincomb(w.XT, Xn, ionic::kRosM1, w.K1, ionic::kRosM2, w.K2, elems, st));
+      // 3. the correction at X~ = XT: b = (X^n - X~ + tau/2 G(X^n; u^n)) + tau/2 G(X~; u^{k+1})
+      IONIC_HIP(ionic::bidomain_current(ce, w.XT, w.uK, g->h, w.idiff2, st));
+      IONIC_HIP(ionic::soa_lincomb(w.B, Xn, -1.0, w.XT, 0.5 * dt, w.FN, elems, st));
+      rc = stage(w.XT, dt, 0.5 * dt, w.B, w.idiff2, on, w.K1);
+      if (rc != IONIC_OK) return rc;
+      // 4. X^{k+1} = X~ + eps and its scaled change from X^k
+      IONIC_HIP(hipMemsetAsync(w.change, 0, sizeof(unsigned long long), st));
+      IONIC_HIP(ionic::imp_finish(w.XT, w.K1, w.XK, n, stride, ns, s->ops->scale, w.change, st));
+      unsigned long long bits = 0;
+      IONIC_HIP(hipMemcpyAsync(&bits, w.change, sizeof(bits), hipMemcpyDeviceToHost, st));
+      IONIC_HIP(hipStreamSynchronize(st));
+      std::memcpy(&change, &bits, sizeof(change));
+      if (change <= inner_tol) break;
+    }
+    if (!(change <= inner_tol)) acc.converged = 0;
+    acc.steps += 1;
+    acc.inner_passes += passes;
+    acc.inner_max = std::max<int32_t>(acc.inner_max, passes);
+    acc.last_change = change;
+    IONIC_HIP(hipMemcpyAsync(Xn, w.XK, state_bytes, hipMemcpyDeviceToDevice, st));
+    IONIC_HIP(hipMemcpyAsync(u_dev, w.uK, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, st));
+  }
+  IONIC_HIP(hipStreamSynchronize(st));
+  acc.cg_iterations = ell.cg_iterations;
   if (info) *info = acc;
   return IONIC_OK;
 }

@@ -31,6 +31,7 @@ struct ModelOps {
   const char* const* param_names;
   const double* param_defaults;  // n_params (+ trailing fixed entries)
   int n_raw;                     // length of the raw parameter vector
+  const double* scale;           // n_states: the Newton stop's per-state scale
   const char* const* state_names;
   size_t params_bytes[2];        // sizeof(Params<double>), sizeof(Params<float>)
   void (*derive)(const double* raw, void* p64, void* p32);

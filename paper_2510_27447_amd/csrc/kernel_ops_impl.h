@@ -125,6 +125,7 @@ struct OpsImpl {
     o.param_names = Model::PARAM_NAMES;
     o.param_defaults = Model::PARAM_DEFAULTS;
     o.n_raw = n_raw();
+    o.scale = Model::SCALE;
     o.state_names = state_names;
     o.params_bytes[0] = sizeof(typename Model::template Params<double>);
     o.params_bytes[1] = sizeof(typename Model::template Params<float>);

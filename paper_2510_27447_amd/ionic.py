@@ -77,6 +77,13 @@ class ionic_bidomain_grid(ctypes.Structure):
                 ("sigma_i", c_double * 3), ("sigma_e", c_double * 3)]
 
 
+class ionic_implicit_info(ctypes.Structure):
+    _fields_ = [("steps", c_int64), ("inner_passes", c_int64), ("cg_iterations", c_int64),
+                ("krylov_iterations", c_int64), ("last_change", c_double),
+                ("inner_max", c_int32), ("converged", c_int32), ("krylov_max", c_int32),
+                ("krylov_converged", c_int32)]
+
+
 class ionic_elliptic_info(ctypes.Structure):
     _fields_ = [("cg_iterations", c_int64), ("relative_residual", c_double),
                 ("converged", c_int32), ("reserved", c_int32)]
@@ -128,6 +135,12 @@ _SIGNATURES = {
                                        c_int, c_int, c_int, c_void_p, c_double, c_double,
                                        c_void_p, c_void_p, c_size_t, c_double, c_int, c_void_p,
                                        POINTER(ionic_elliptic_info), c_void_p]),
+    "ionic_implicit_work_bytes": (c_size_t, [c_int, c_int64, c_int64, c_int64, c_int]),
+    "reaction_bidomain_implicit_step": (c_int, [c_void_p, POINTER(ionic_bidomain_grid), c_double,
+                                                c_double, c_int, c_void_p, c_double, c_double,
+                                                c_void_p, c_void_p, c_size_t, c_double, c_double,
+                                                c_double, c_int, c_int,
+                                                POINTER(ionic_implicit_info), c_void_p]),
     "ionic_set_inputs": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_void_p, c_double,
                                  c_double, c_void_p]),
     "reaction_sdc_step_batch": (c_int, [POINTER(c_void_p), POINTER(c_int), c_int, c_void_p]),
@@ -331,6 +344,23 @@ def reaction_bidomain_step(handle, grid, t0, dt, n_steps, n_nodes, n_sweeps, u, 
                                         _ptr(work), work_bytes, rtol, max_iter, _ptr(i_diff_work),
                                         ctypes.byref(info), _stream(stream)))
     return _info_dict(info)
+
+
+def ionic_implicit_work_bytes(model, nx, ny, nz, max_iter):
+    return lib().ionic_implicit_work_bytes(MODEL_IDS.get(model, model), nx, ny, nz, max_iter)
+
+
+def reaction_bidomain_implicit_step(handle, grid, t0, dt, n_steps, u, work, work_bytes,
+                                    i_stim=None, stim_t_on=0.0, stim_t_off=0.0,
+                                    elliptic_rtol=1e-10, krylov_rtol=1e-10, inner_tol=1e-8,
+                                    max_inner=30, max_iter=1000, stream=None):
+    info = ionic_implicit_info()
+    _check(lib().reaction_bidomain_implicit_step(handle, ctypes.byref(grid), t0, dt, n_steps,
+                                                 _ptr(i_stim), stim_t_on, stim_t_off, _ptr(u),
+                                                 _ptr(work), work_bytes, elliptic_rtol, krylov_rtol,
+                                                 inner_tol, max_inner, max_iter,
+                                                 ctypes.byref(info), _stream(stream)))
+    return {name: getattr(info, name) for name, _ in ionic_implicit_info._fields_}
 
 
 def ionic_set_inputs(handle, t0, dt, n_nodes, n_sweeps, i_stim=None, stim_t_on=0.0,

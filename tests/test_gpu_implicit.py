@@ -1,0 +1,95 @@
+"""GPU vs oracle for partitioned stepping with the parabolic term implicit
+(paper section 3.3.2, Algorithm 2 with the inner loop; section 3.3.1, ROS2;
+equation sdc), through the C ABI (reaction_bidomain_implicit_step).
+
+The oracle (oracle/partitioned.py) solves every global stage and correction
+system directly; the library eliminates each vertex's block onto V and runs
+BiCGSTAB on the grid.  Both stop the inner loop at a scaled change of 1e-12
+(the GPU's Krylov and CG solves at 1e-13), so they settle on the same fixed
+point; the bar is the fp64 path's 1e-10 of max|V| on V and 1e-9 of each
+state's scale max(max|X_i|, s_i) on every state.  Steps of 0.05 ms at
+h = 0.01 cm (the paper's largest adaptive step; beyond the explicit limit
+of reaction_bidomain_step) with the paper's sigma_i = sigma_e = 1.5e-3, on
+sheets and a small slab (multigrid for the elliptic solve), a stimulated
+edge, both cell models; and the linear test model on a cable, where each
+cosine mode is multiplied by the scheme's amplification."""
+import numpy as np
+import pytest
+
+from gpu_helpers import MODEL_OF, gpu_tensor, say
+from oracle.diffusion import Bidomain
+from oracle.partitioned import advance_partitioned
+from paper_2510_27447_amd.workloads import initial_state
+
+pytestmark = pytest.mark.gpu
+
+SIG = (1.5e-3,) * 3
+
+
+def run_both(model, x0, shape, stim, n_steps, dt=0.05, h=0.01, precision="fp64", params=None,
+             t_off=1.0):
+    import torch
+    from paper_2510_27447_amd import ionic as I
+    n = x0.shape[1]
+    bd = Bidomain(shape, h, SIG, SIG)
+    u0 = bd.elliptic(x0[0])
+    mdl = MODEL_OF[model]
+    if params:
+        mdl = mdl.with_params(**params)
+    Xo, uo, st = advance_partitioned(mdl, x0, u0, bd, dt=dt, n_steps=n_steps, i_stim=stim,
+                                     stim_on=0.0, stim_off=t_off, tol=1e-12, max_inner=60)
+    sim = I.Simulation(model, x0, precision=precision,
+                       params=None if not params else [params[k] for k in params])
+    u = torch.as_tensor(u0).cuda()
+    max_iter = 2000
+    wb = I.ionic_implicit_work_bytes(model, *shape, max_iter)
+    work = torch.zeros(wb, dtype=torch.uint8, device="cuda")
+    g = I.make_bidomain_grid(*shape, h=h, sigma_i=SIG, sigma_e=SIG)
+    info = I.reaction_bidomain_implicit_step(sim.handle, g, 0.0, dt, n_steps, u, work, wb,
+                                             gpu_tensor(stim), 0.0, t_off, elliptic_rtol=1e-13,
+                                             krylov_rtol=1e-13, inner_tol=1e-12, max_inner=60,
+                                             max_iter=max_iter)
+    Xg = sim.readback()
+    ug = u.cpu().numpy()
+    sim.close()
+    return Xo, uo, st, Xg, ug, info
+
+
+def check(model, Xg, Xo, ug, uo):
+    mdl = MODEL_OF[model]
+    ev = np.max(np.abs(Xg[0] - Xo[0])) / np.max(np.abs(Xo[0]))
+    scale = np.maximum(np.max(np.abs(Xo), axis=1), mdl.newton_scale)
+    serr = np.max(np.abs(Xg - Xo), axis=1) / scale
+    eu = np.max(np.abs(ug - uo)) / max(np.max(np.abs(uo)), 1e-300)
+    say("  V %.2e, worst state %.2e (%s), u %.2e" % (ev, serr.max(),
+                                                    mdl.state_names[int(np.argmax(serr))], eu))
+    assert ev <= 1e-10
+    assert np.all(serr <= 1e-9), serr
+    assert eu <= 1e-9
+
+
+@pytest.mark.parametrize("model", ["LR91", "TT06"])
+@pytest.mark.parametrize("shape", [(12, 10, 1), (6, 5, 4)], ids=["sheet", "slab"])
+def test_implicit_partitioned_matches_oracle(model, shape):
+    n = int(np.prod(shape))
+    rng = np.random.Generator(np.random.PCG64(31))
+    x0 = np.tile(initial_state(model)[:, None], (1, n))
+    x0[0] += rng.uniform(-1.0, 1.0, n)
+    stim = np.where(np.arange(n) % shape[0] < 2, -100.0, 0.0)
+    say("case", model, shape)
+    Xo, uo, st, Xg, ug, info = run_both(model, x0, shape, stim, n_steps=12)
+    say("  gpu", info, "oracle passes", st.inner_iterations)
+    assert info["converged"] == 1 and info["krylov_converged"] == 1
+    assert np.all(np.isfinite(Xg))
+    check(model, Xg, Xo, ug, uo)
+
+
+@pytest.mark.parametrize("k", [1, 16, 32])
+def test_linear_cable_modes(k):
+    nx = 33
+    phi = np.cos(k * np.pi * np.arange(nx) / (nx - 1))
+    x0 = phi[None, :].copy()
+    Xo, uo, st, Xg, ug, info = run_both("TEST_LINEAR", x0, (nx, 1, 1), np.zeros(nx), n_steps=3,
+                                        params={"lam": -0.3, "b": 0.0})
+    say("mode", k, info)
+    check("TEST_LINEAR", Xg, Xo, ug, uo)
