@@ -599,6 +599,59 @@ def microbench(torch):
     return out
 
 
+def run_bidomain_implicit(I, torch, w, n_steps=10, dt=0.05, h=0.01, sigma=1.5e-3,
+                          inner_tol=1e-6, rtol=1e-8, max_iter=2000):
+    """Algorithm 2 in full on the slab (reaction_bidomain_implicit_step): per
+    step, inner passes of the elliptic solve and ROS2 + one correction with the
+    parabolic term inside the stages, at the paper's largest step dt = 0.05 ms
+    (beyond the explicit limit h^2 / (2 sigma_i) = 0.033 ms at h = 0.01 cm),
+    stimulus on the first five x-planes for 1 ms.  One untimed run of 2 steps,
+    then one timed run of n_steps from the same state."""
+    sim = I.Simulation(w.model, w.x0, precision="fp64")
+    stim = torch.as_tensor(np.where(np.arange(w.n) % w.grid[0] < 5, -100.0, 0.0)).cuda()
+    g = I.make_bidomain_grid(*w.grid, h=h, sigma_i=(sigma,) * 3, sigma_e=(sigma,) * 3)
+    wb = I.ionic_implicit_work_bytes(w.model, *w.grid, max_iter)
+    work = torch.zeros(wb, dtype=torch.uint8, device="cuda")
+    ewb = I.ionic_elliptic_work_bytes(*w.grid, max_iter)
+    ework = torch.zeros(ewb, dtype=torch.uint8, device="cuda")
+    u = torch.zeros(w.n, dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    I.ionic_elliptic_solve(sim.handle, g, u, ework, ewb, rtol=rtol, max_iter=max_iter,
+                           stream=stream)
+    init, u_init = sim.state.clone(), u.clone()
+
+    def run(steps):
+        sim.state.copy_(init)
+        u.copy_(u_init)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = I.reaction_bidomain_implicit_step(sim.handle, g, 0.0, dt, steps, u, work, wb, stim,
+                                                 0.0, 1.0, elliptic_rtol=rtol, krylov_rtol=rtol,
+                                                 inner_tol=inner_tol, max_inner=40,
+                                                 max_iter=max_iter, stream=stream)
+        torch.cuda.synchronize()
+        return info, time.perf_counter() - t0
+
+    run(2)
+    info, wall = run(n_steps)
+    V = sim.readback(count=None)[0]
+    sim.close()
+    levels = I.ionic_multigrid_levels(*w.grid)
+    return {
+        "steps": n_steps, "dt_ms": dt, "ms_per_step": wall / n_steps * 1e3,
+        "value": w.n * n_steps / wall,
+        "inner_passes_per_step": info["inner_passes"] / n_steps, "inner_max": info["inner_max"],
+        "inner_tol": inner_tol, "converged": info["converged"],
+        "cg_iterations_per_pass": info["cg_iterations"] / info["inner_passes"],
+        "krylov_iterations_per_solve": info["krylov_iterations"] / (3 * info["inner_passes"]),
+        "krylov_max": info["krylov_max"], "rtol": rtol,
+        "multigrid_levels": levels,
+        "launches_per_cycle": 4 * levels - 3 if levels else 0,
+        "coarse_level_launches_per_cycle": 4 * levels - 7 if levels else 0,
+        "V_range_mV": [float(np.min(V)), float(np.max(V))],
+    }
+
+
 def cpu_workers():
     try:
         avail = len(os.sched_getaffinity(0))
@@ -827,6 +880,12 @@ def main():
         w = W.c2_tt06(precision="mixed")
         print("[bench] partitioned bidomain mixed", file=sys.stderr, flush=True)
         bido = run_bidomain(I, torch, w)
+        w = W.c2_tt06(precision="fp64")
+        print("[bench] partitioned bidomain, parabolic term implicit, fp64", file=sys.stderr,
+              flush=True)
+        bido["implicit"] = run_bidomain_implicit(I, torch, w)
+        print("[bench] implicit: %.1f ms per step" % bido["implicit"]["ms_per_step"],
+              file=sys.stderr, flush=True)
 
     serving = None
     if not args.no_serving:

@@ -309,6 +309,12 @@ int reaction_diffusion_step(ionic_sim* sim, const ionic_grid* grid, double t0, d
                             double stim_t_on, double stim_t_off, double* i_diff_work_dev,
                             void* hip_stream);
 
+/* Levels of the multigrid hierarchy the elliptic solve uses on this grid
+ * (fine level included), 0 when the grid is small enough for the Jacobi
+ * preconditioner.  One preconditioner application (a V-cycle) on L levels
+ * is 4 L - 3 kernel launches, 4 L - 7 of them on the coarse levels.  Host only. */
+int ionic_multigrid_levels(int64_t nx, int64_t ny, int64_t nz);
+
 /* Device bytes of the work buffer of ionic_elliptic_solve and
  * reaction_bidomain_step for this grid and iteration cap (0 on bad sizes). */
 size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_iter);

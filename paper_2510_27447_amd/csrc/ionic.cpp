@@ -529,6 +529,14 @@ static size_t elliptic_bytes(long long nx, long long ny, long long nz, int max_i
          sizeof(double) * ionic::mg_doubles(ionic::mg_plan(nx, ny, nz));
 }
 
+int ionic_multigrid_levels(int64_t nx, int64_t ny, int64_t nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(IONIC_EINVAL, "grid extents must be >= 1");
+  if ((__int128)nx * ny * nz >= ((__int128)1 << 31))
+    return fail(IONIC_EINVAL, "grid must have fewer than 2^31 nodes");
+  const ionic::MgPlan plan = ionic::mg_plan(nx, ny, nz);
+  return plan.usable ? plan.levels : 0;
+}
+
 size_t ionic_elliptic_work_bytes(int64_t nx, int64_t ny, int64_t nz, int max_iter) {
   if (nx < 1 || ny < 1 || nz < 1 || max_iter < 0 || max_iter > (1 << 24)) return 0;
   if ((__int128)nx * ny * nz >= ((__int128)1 << 31)) return 0;

@@ -127,6 +127,7 @@ _SIGNATURES = {
     "reaction_diffusion_step": (c_int, [c_void_p, POINTER(ionic_grid), c_double, c_double, c_int,
                                         c_int, c_int, c_void_p, c_double, c_double, c_void_p,
                                         c_void_p]),
+    "ionic_multigrid_levels": (c_int, [c_int64, c_int64, c_int64]),
     "ionic_elliptic_work_bytes": (c_size_t, [c_int64, c_int64, c_int64, c_int]),
     "ionic_elliptic_solve": (c_int, [c_void_p, POINTER(ionic_bidomain_grid), c_void_p, c_void_p,
                                      c_size_t, c_double, c_int, POINTER(ionic_elliptic_info),
@@ -316,6 +317,13 @@ def reaction_diffusion_step(handle, grid, t0, dt, n_steps, n_nodes, n_sweeps, wo
     _check(lib().reaction_diffusion_step(handle, ctypes.byref(grid), t0, dt, n_steps, n_nodes,
                                          n_sweeps, _ptr(i_stim), stim_t_on, stim_t_off, _ptr(work),
                                          _stream(stream)))
+
+
+def ionic_multigrid_levels(nx, ny, nz):
+    n = lib().ionic_multigrid_levels(nx, ny, nz)
+    if n < 0:
+        _check(n)
+    return n
 
 
 def ionic_elliptic_work_bytes(nx, ny, nz, max_iter):

@@ -190,3 +190,19 @@ def test_elliptic_work_bytes_and_rejections():
                                     I.ctypes.byref(info), None) == -1
     assert lib.reaction_bidomain_step(None, I.ctypes.byref(g), 0.0, 0.02, 1, 3, 2, None, 0.0, 0.0,
                                       None, None, 0, 1e-8, 10, None, None, None) == -1
+
+
+def test_multigrid_levels_and_implicit_work_size():
+    """Host-only queries of the elliptic hierarchy and the implicit step's work
+    buffer: the slab coarsens 100 -> 51 -> 26 -> 14 -> 8 (5 levels), grids of at
+    most 512 nodes use Jacobi (0 levels), bad extents are rejected."""
+    assert I.ionic_multigrid_levels(100, 100, 100) == 5
+    assert I.ionic_multigrid_levels(8, 8, 8) == 0
+    assert I.ionic_multigrid_levels(60, 50, 1) == 3
+    with pytest.raises(I.IonicError):
+        I.ionic_multigrid_levels(0, 4, 4)
+    b = I.ionic_implicit_work_bytes("TT06", 100, 100, 100, 2000)
+    # six state-sized vectors (19 planes of 1e6 doubles) dominate
+    assert 6 * 19 * 8e6 < b < 6 * 19 * 8e6 + 300e6
+    assert I.ionic_implicit_work_bytes("TT06", 0, 1, 1, 10) == 0
+    assert I.ionic_implicit_work_bytes(7, 4, 4, 4, 10) == 0
