@@ -379,7 +379,9 @@ size_t ionic_implicit_work_bytes(int model, int64_t nx, int64_t ny, int64_t nz, 
  * eliminated onto V by the static sparse elimination, the remaining system
  * (S + c M_L^{-1} A_i) dv = r over the grid is solved by BiCGSTAB (the
  * paper's Krylov method) preconditioned by its diagonal to ||r|| <=
- * krylov_rtol ||r_0||, and each vertex's states follow from dv.  Any step
+ * krylov_rtol ||b|| (b the reduced right-hand side), starting from the same
+ * system's solution in the previous pass of the call (from zero in the
+ * first pass), and each vertex's states follow from dv.  Any step
  * size is stable (dt = 0.05 ms at h = 0.01 cm, the paper's largest step, is
  * beyond reaction_bidomain_step's explicit limit).
  *  u_dev: N doubles, device: u^0 on entry (e.g. from ionic_elliptic_solve),

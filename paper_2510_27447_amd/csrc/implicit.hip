@@ -286,44 +286,61 @@ __device__ __forceinline__ void apply_op(const CgParams& c, double inv_h2, doubl
   }
 }
 
+// the start of a solve from the guess in w.x (zero unless warm): r = rhs - A x,
+// r^ = r, p = v = 0, the inverse diagonal, and the parts of r^.r, r.r and rhs.rhs
 __global__ void __launch_bounds__(kThreads)
     bicg_start_kernel(CgParams c, double inv_h2, double cst, const double* __restrict__ S,
-                      const double* __restrict__ rhs, BiCgWork w) {
+                      const double* __restrict__ rhs, BiCgWork w, int warm) {
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     ctl_of(w)->done = 0;
     ctl_of(w)->reserved = 0;
     ctl_of(w)->iters = 0;
   }
-  double s[2] = {0.0, 0.0};  // r^.r, r.r
-  for (long long v = my_span(c).first, e = my_span(c).end; v < e; v += kThreads) {
-    const Q1Coords q = q1_coords(v, c.nx, c.ny);
+  double s[3] = {0.0, 0.0, 0.0};  // r^.r, r.r, rhs.rhs
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const long long begin = chunk_id(c) * c.chunk;
+  const long long end = begin + c.chunk < c.n ? begin + c.chunk : c.n;
+  const double* const x = w.x;
+  const auto x_of = [x, warm](long long t) { return warm ? x[t] : 0.0; };
+  for (long long first = begin + wave * kLanesOut; first < end; first += kWaves * kLanesOut) {
+    const long long v = first - 1 + lane;
+    const long long vl = v < 0 ? 0 : (v < c.n ? v : c.n - 1);
+    const Q1Coords q = q1_coords(vl, c.nx, c.ny);
     const Q1Node node(q.i, q.j, q.k, c.nx, c.ny, c.nz);
-    const double d = S[v] + cst * inv_h2 * node.diag(c.si) / node.mass();
-    w.dinv[v] = 1.0 / d;
-    const double b = rhs[v];
-    w.x[v] = 0.0;
-    w.r[v] = b;
-    w.rh[v] = b;
-    w.p[v] = 0.0;
-    w.v[v] = 0.0;
-    s[0] += b * b;
-    s[1] += b * b;
+    double xv;
+    const double ax = node.apply_lanes(x_of, c.si, xv);
+    if (lane >= 1 && lane <= kLanesOut && v < end) {
+      const double m = node.mass();
+      w.dinv[v] = 1.0 / (S[v] + cst * inv_h2 * node.diag(c.si) / m);
+      const double b = rhs[v];
+      const double r = b - (S[v] * xv + cst * inv_h2 * ax / m);
+      if (!warm) w.x[v] = 0.0;
+      w.r[v] = r;
+      w.rh[v] = r;
+      w.p[v] = 0.0;
+      w.v[v] = 0.0;
+      s[0] += r * r;
+      s[1] += r * r;
+      s[2] += b * b;
+    }
   }
-  double* const part[2] = {w.part[0], w.part[1]};
+  double* const part[3] = {w.part[0], w.part[1], w.part[2]};
   put_partials(s, part, c);
 }
 
 // A: the test of ||r_k||, then the direction p = r + beta (p - omega v), p^ = p / D
 __global__ void __launch_bounds__(kThreads) bicg_dir_kernel(CgParams c, BiCgWork w, long long k) {
   if (ctl_of(w)->done) return;
-  const double* const in[2] = {w.part[0], w.part[1]};
-  double t[2];  // rho_k = r^.r_k, r_k.r_k
+  // rho_k = r^.r_k, r_k.r_k, and at k = 0 rhs.rhs (part 2 holds it until v = A p^;
+  // later it holds r^.v of the previous iteration, summed and not used)
+  const double* const in[3] = {w.part[0], w.part[1], w.part[2]};
+  double t[3];
   total_of(in, c, t);
-  const double bb = k == 0 ? t[1] : w.sc[0];
+  const double bb = k == 0 ? t[2] : w.sc[0];
   const double rel = bb > 0.0 ? ::sqrt(t[1] / bb) : 0.0;
   const bool stop = !(rel > c.rtol);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    if (k == 0) w.sc[0] = t[1];
+    if (k == 0) w.sc[0] = t[2];
     iter_sc(w, k)[0] = t[0];
     iter_sc(w, k)[3] = t[1];
     if (stop) {
@@ -452,9 +469,9 @@ hipError_t imp_finish(const double* XT, const double* eps, double* XK, long long
 }
 
 hipError_t bicg_start(const CgParams& c, double h, double cst, const double* S, const double* rhs,
-                      BiCgWork& w, hipStream_t st) {
+                      BiCgWork& w, int warm, hipStream_t st) {
   hipLaunchKernelGGL(bicg_start_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, c,
-                     1.0 / (h * h), cst, S, rhs, w);
+                     1.0 / (h * h), cst, S, rhs, w, warm);
   return hipGetLastError();
 }
 

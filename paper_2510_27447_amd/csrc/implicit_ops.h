@@ -54,15 +54,17 @@ hipError_t imp_finish(const double* XT, const double* eps, double* XK, long long
 // sigma_i, M_L the lumped mass), preconditioned by its diagonal.  Work: the
 // BiCgWork vectors; the solve runs until ||r_k|| <= rtol ||r_0|| or max_iter.
 struct BiCgWork {
-  double *x, *r, *rh, *p, *ph, *v, *s, *sh, *t, *dinv;  // n each
+  double* x;                                        // n: the solution (and the guess when warm)
+  double *r, *rh, *p, *ph, *v, *s, *sh, *t, *dinv;  // n each
   double* part[5];                                      // nb each: r^.r, r.r, r^.v, t.s, t.t
   double* sc;  // scalars: [0] b.b, [1] rho, [2] alpha, [3] omega, [4..5] ctl, then r.r per iteration
   static size_t bytes(long long n, long long nb, int max_iter) {
     return sizeof(double) * size_t(10 * n + 5 * nb + 8 + 4 * (max_iter + 2));
   }
 };
+// the start of a solve; with warm != 0 from the guess already in w.x, else from zero
 hipError_t bicg_start(const CgParams& c, double h, double cst, const double* S, const double* rhs,
-                      BiCgWork& w, hipStream_t st);
+                      BiCgWork& w, int warm, hipStream_t st);
 // iteration k: no work once the device has found convergence
 hipError_t bicg_iteration(const CgParams& c, double h, double cst, const double* S, int k,
                           BiCgWork& w, hipStream_t st);

@@ -790,12 +790,15 @@ namespace {
 
 // Layout of the work buffer of reaction_bidomain_implicit_step: the elliptic
 // solve's work, six state-sized vectors (n_states planes of stride doubles),
-// five fields of stride doubles, the BiCGSTAB work and one change slot.
+// five fields of stride doubles, the BiCGSTAB work, the solutions of the three
+// systems of a pass (each the guess of the same system in the next pass) and
+// one change slot.
 struct ImpWork {
   void* elliptic;
   double *XK, *K1, *K2, *XT, *FN, *B;  // state-sized
   double *idiff, *idiff2, *S, *r, *uK;  // fields
   ionic::BiCgWork bw;
+  double* xs[3];  // xs[0] is the BiCGSTAB work's own x
   unsigned long long* change;
 };
 
@@ -803,7 +806,7 @@ size_t imp_bytes(int n_states, long long nx, long long ny, long long nz, int max
   const long long n = nx * ny * nz, stride = stride_of(n);
   const ionic::CgParams c = ionic::cg_params(nx, ny, nz);
   const size_t ell = (elliptic_bytes(nx, ny, nz, max_iter) + 255) / 256 * 256;
-  return ell + sizeof(double) * size_t(6 * n_states * stride + 5 * stride) +
+  return ell + sizeof(double) * size_t(6 * n_states * stride + 5 * stride + 2 * n) +
          ionic::BiCgWork::bytes(n, c.nb, max_iter) + 256;
 }
 
@@ -831,6 +834,11 @@ ImpWork carve_imp(void* work, int n_states, long long nx, long long ny, long lon
     *v = q;
     q += n;
   }
+  w.xs[0] = w.bw.x;
+  for (int a = 1; a < 3; ++a) {
+    w.xs[a] = q;
+    q += n;
+  }
   for (int a = 0; a < 5; ++a) {
     w.bw.part[a] = q;
     q += c.nb;
@@ -841,22 +849,32 @@ ImpWork carve_imp(void* work, int n_states, long long nx, long long ny, long lon
   return w;
 }
 
-// One BiCGSTAB solve of (S + cst M_L^{-1} A_i) x = r into w.bw.x; iterations
-// in batches with one synchronisation each.  Adds to the counters of info.
-int bicg_solve(const ionic::CgParams& c, double h, double cst, ImpWork& w, int max_iter,
-               ionic_implicit_info* acc, hipStream_t st) {
-  IONIC_HIP(ionic::bicg_start(c, h, cst, w.S, w.r, w.bw, st));
+// One BiCGSTAB solve of (S + cst M_L^{-1} A_i) x = r into w.xs[sys], from the
+// value xs[sys] holds when warm (the same system's solution in the previous
+// pass or step), else from zero.  Iterations go in batches with one
+// synchronisation each, the first sized from `expect` (the previous solve's
+// count); launches queued after convergence return at once.  Adds to the
+// counters of info and returns the iteration count in *iters_out.
+int bicg_solve(const ionic::CgParams& c, double h, double cst, ImpWork& w, int sys, int warm,
+               long long expect, int max_iter, ionic_implicit_info* acc, long long* iters_out,
+               hipStream_t st) {
+  w.bw.x = w.xs[sys];
+  IONIC_HIP(ionic::bicg_start(c, h, cst, w.S, w.r, w.bw, warm, st));
   constexpr int kBatch = 4;
   int k = 0;
   ionic::BiCgCtl ctl{0, 0, 0};
+  // iteration k's first launch tests ||r_k||: a solve of m iterations ends in launch m
+  int batch = int(std::min<long long>(std::max<long long>(kBatch, expect + 1), max_iter + 1));
   for (;;) {
-    const int until = std::min(max_iter + 1, k + kBatch);
+    const int until = std::min(max_iter + 1, k + batch);
+    batch = kBatch;
     for (; k < until; ++k) IONIC_HIP(ionic::bicg_iteration(c, h, cst, w.S, k, w.bw, st));
     IONIC_HIP(hipMemcpyAsync(&ctl, w.bw.sc + 4, sizeof(ctl), hipMemcpyDeviceToHost, st));
     IONIC_HIP(hipStreamSynchronize(st));
     if (ctl.done || k > max_iter) break;
   }
   const long long iters = ctl.done ? ctl.iters : max_iter;
+  *iters_out = iters;
   acc->krylov_iterations += iters;
   acc->krylov_max = std::max<int32_t>(acc->krylov_max, int32_t(iters));
   if (!ctl.done) acc->krylov_converged = 0;
@@ -916,10 +934,15 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
   acc.converged = 1;
   acc.krylov_converged = 1;
   ionic_elliptic_info ell{0, 0.0, 1, 0};
+  long long cg_last = 0;
 
-  // one stage or correction system: reduce at X, BiCGSTAB, expand into out
-  auto stage = [&](const double* X, double c, double cf, const double* base, const double* idiff,
-                   int stim_on, double* out) -> int {
+  // one stage or correction system (sys 0, 1, 2): reduce at X, BiCGSTAB, expand
+  // into out.  Each system's solve starts from its own solution in the last pass
+  // (of this step or the previous one), from zero in the first pass of the call.
+  long long krylov_last[3] = {0, 0, 0};
+  int have_guess[3] = {0, 0, 0};
+  auto stage = [&](int sys, const double* X, double c, double cf, const double* base,
+                   const double* idiff, int stim_on, double* out) -> int {
     ionic::ImpBlock b{};
     b.X = X;
     b.n = n;
@@ -934,10 +957,12 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
     b.S = w.S;
     b.r = w.r;
     IONIC_HIP(ionic::imp_block(model, p64, b, st));
-    int rc2 = bicg_solve(ck, g->h, c, w, max_iter, &acc, st);
+    int rc2 = bicg_solve(ck, g->h, c, w, sys, have_guess[sys], krylov_last[sys], max_iter, &acc,
+                         &krylov_last[sys], st);
     if (rc2 != IONIC_OK) return rc2;
+    have_guess[sys] = 1;
     b.expand = 1;
-    b.dv = w.bw.x;
+    b.dv = w.xs[sys];
     b.out = out;
     IONIC_HIP(ionic::imp_block(model, p64, b, st));
     return IONIC_OK;
@@ -957,24 +982,26 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
     for (int k = 0; k < max_inner; ++k) {
       ++passes;
       // 1. u^{k+1} from v^k
-      rc = elliptic_solve_impl(s, ce, w.uK, w.elliptic, elliptic_rtol, max_iter, pc, &ell, st, 0,
-                               w.XK);
+      const long long cg_before = ell.cg_iterations;
+      rc = elliptic_solve_impl(s, ce, w.uK, w.elliptic, elliptic_rtol, max_iter, pc, &ell, st,
+                               cg_last, w.XK);
       if (rc != IONIC_OK) return rc;
+      cg_last = ell.cg_iterations - cg_before;
       // 2. ROS2 from X^n with u^{k+1}, both stages on I - gamma tau J(X^n)
       IONIC_HIP(ionic::bidomain_current(ce, Xn, w.uK, g->h, w.idiff, st));
-      rc = stage(Xn, kG * dt, kG * dt, nullptr, w.idiff, on, w.K1);
+      rc = stage(0, Xn, kG * dt, kG * dt, nullptr, w.idiff, on, w.K1);
       if (rc != IONIC_OK) return rc;
       IONIC_HIP(ionic::soa_lincomb(w.XT, Xn, ionic::kRosA21, w.K1, 0.0, nullptr, elems, st));
       IONIC_HIP(ionic::bidomain_current(ce, w.XT, w.uK, g->h, w.idiff2, st));
       IONIC_HIP(ionic::imp_rhs(model, p64, w.XT, n, stride, i_stim_dev, on, w.idiff2, kG * dt,
                                -2.0, w.K1, w.B, st));
-      rc = stage(Xn, kG * dt, 0.0, w.B, w.idiff, on, w.K2);
+      rc = stage(1, Xn, kG * dt, 0.0, w.B, w.idiff, on, w.K2);
       if (rc != IONIC_OK) return rc;
       IONIC_HIP(ionic::soa_lincomb(w.XT, Xn, ionic::kRosM1, w.K1, ionic::kRosM2, w.K2, elems, st));
       // 3. the correction at X~ = XT: b = (X^n - X~ + tau/2 G(X^n; u^n)) + tau/2 G(X~; u^{k+1})
       IONIC_HIP(ionic::bidomain_current(ce, w.XT, w.uK, g->h, w.idiff2, st));
       IONIC_HIP(ionic::soa_lincomb(w.B, Xn, -1.0, w.XT, 0.5 * dt, w.FN, elems, st));
-      rc = stage(w.XT, dt, 0.5 * dt, w.B, w.idiff2, on, w.K1);
+      rc = stage(2, w.XT, dt, 0.5 * dt, w.B, w.idiff2, on, w.K1);
       if (rc != IONIC_OK) return rc;
       // 4. X^{k+1} = X~ + eps and its scaled change from X^k
       IONIC_HIP(hipMemsetAsync(w.change, 0, sizeof(unsigned long long), st));
