@@ -6,7 +6,9 @@ simulation's ionic state resident in HBM and advances all simulations of one
 class (cell model x precision x node count, the unit one kernel instantiation
 serves) together: each round launches one batched kernel per class over a
 chunk of steps (reaction_sdc_step_batch), on one stream per class so the
-classes overlap on the GPU.  Between chunks it retires finished requests
+classes overlap on the GPU.  A chunk is at least chunk_steps steps and at least
+quantum_vertices * chunk_steps vertex-steps, so a small request finishes in
+one round instead of waiting out as many rounds as a large one.  Between chunks it retires finished requests
 (their final V is copied to the host) and admits arrivals in FIFO order while
 the resident footprint stays within the HBM budget and a slot is free; neither
 step waits for the device.  A request computes exactly what it computes alone:
@@ -66,6 +68,16 @@ class Admission:
         return admitted, rejected
 
 
+def chunk_for(n: int, remaining: int, chunk_steps: int, quantum_vertices: int) -> int:
+    """Steps a job of n vertices takes in one round: chunk_steps, or more for a
+    job smaller than quantum_vertices, so that it does chunk_steps *
+    quantum_vertices vertex-steps; never more than it has left."""
+    steps = chunk_steps
+    if quantum_vertices > 0 and n > 0:
+        steps = max(steps, (chunk_steps * quantum_vertices) // n)
+    return max(0, min(remaining, steps))
+
+
 @dataclass
 class _Job:
     req: object
@@ -102,8 +114,9 @@ class Result:
 @dataclass
 class Server:
     budget_bytes: float = 200e9
-    slots: int = 64
-    chunk_steps: int = 100
+    slots: int = 128
+    chunk_steps: int = 50
+    quantum_vertices: int = 400_000     # jobs below this many vertices take longer chunks
     keep_state: bool = False            # keep each result's full state (tests)
     results: List[Result] = field(default_factory=list)
     rejected: List[int] = field(default_factory=list)
@@ -243,7 +256,8 @@ class Server:
                     if not j.waited:
                         st.wait_event(j.ready)
                         j.waited = True
-                steps = [min(self.chunk_steps, j.remaining) for j in jobs]
+                steps = [chunk_for(j.sim.n, j.remaining, self.chunk_steps, self.quantum_vertices)
+                         for j in jobs]
                 I.reaction_sdc_step_batch([j.sim.handle for j in jobs], steps, stream=st)
                 ev = torch.cuda.Event()
                 ev.record(st)
@@ -281,6 +295,7 @@ def run_trace(trace, verbose=False, **server_kw):
     res = srv.run(trace, verbose=verbose)
     out = summarize(res, srv.rejected)
     out.update({"budget_bytes": srv.budget_bytes, "slots": srv.slots, "chunk_steps": srv.chunk_steps,
+                "quantum_vertices": srv.quantum_vertices,
                 "trace": "256 requests, Poisson 20/s, N log-uniform [1e3, 2e6], LR91/TT06, "
                          "fp64/mixed, dt {0.01, 0.02}, steps U{100..1000}, M=3, K=2"})
     return out

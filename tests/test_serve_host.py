@@ -47,3 +47,16 @@ def test_trace_shape():
     assert sum(r.footprint_bytes() for r in tr) < 200e9
     w = tr[3].materialize()
     assert w.x0.shape[1] == tr[3].n and np.count_nonzero(w.i_stim) == max(1, tr[3].n // 10)
+
+
+def test_chunk_sizes():
+    from paper_2510_27447_amd.serve import chunk_for
+    # large jobs take the plain chunk, small ones the same vertex-steps, capped by what is left
+    assert chunk_for(2_000_000, 1000, 100, 200_000) == 100
+    assert chunk_for(200_000, 1000, 100, 200_000) == 100
+    assert chunk_for(100_000, 1000, 100, 200_000) == 200
+    assert chunk_for(1_000, 1000, 100, 200_000) == 1000
+    assert chunk_for(1_000, 37, 100, 200_000) == 37
+    assert chunk_for(5_000, 0, 100, 200_000) == 0
+    # without a quantum every job takes the plain chunk
+    assert chunk_for(1_000, 1000, 100, 0) == 100
