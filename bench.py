@@ -91,7 +91,7 @@ def traffic_from_counters(fetch_csv, write_csv):
         for r in rows:
             v = float(r["Counter_Value"]) * 1024.0
             name = r["Kernel_Name"]
-            if "sdc_kernel" in name:
+            if "sdc_kernel" in name and "TT06" in name:
                 # the Newton kernels: predictor 0, the last template argument
                 if not name.split(">")[0].rstrip().endswith("0"):
                     continue
@@ -469,7 +469,8 @@ def valu_mix(csv_paths, n_steps=500):
         seen = {}
         for r in csv.DictReader(open(path)):
             name = r["Kernel_Name"]
-            if "sdc_kernel" not in name or not name.split(">")[0].rstrip().endswith("0"):
+            if ("sdc_kernel" not in name or "TT06" not in name
+                    or not name.split(">")[0].rstrip().endswith("0")):
                 continue
             prec = "fp64" if "Fp64" in name else "mixed"
             d = seen.setdefault(prec, r["Dispatch_Id"])
@@ -717,6 +718,42 @@ def state_errors(Xg, Xo, names):
     return out
 
 
+def run_c1(I, torch):
+    """C1, the plain LR91 method in fp64: 4096 vertices (64 x 64), 1000 steps of
+    0.02 ms, 3 nodes, 2 sweeps, in one fused launch; one untimed pass, then one
+    timed pass from the same state.  64 workgroups: a quarter of the compute
+    units hold one wavefront each, so this is a latency figure, not a
+    throughput one."""
+    from paper_2510_27447_amd import workloads as W
+    w = W.c1_lr91()
+    sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
+                       newton_maxit=w.newton_maxit)
+    stim = torch.as_tensor(w.i_stim).cuda()
+    init = sim.state.clone()
+    stream = torch.cuda.current_stream()
+
+    def one():
+        sim.state.copy_(init)
+        I.ionic_reset_stats(sim.handle)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        sim.step(0.0, w.dt, w.n_steps, w.n_nodes, w.n_sweeps, stim, w.stim_t_on, w.stim_t_off,
+                 None, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    one()
+    secs = one()
+    st = sim.stats()
+    sim.close()
+    return {"value": w.n * w.n_steps / secs, "kernel_ms": secs * 1e3, "vertices": w.n,
+            "steps": w.n_steps, "workgroups": (w.n + 63) // 64,
+            "newton_iters_per_solve": st["newton_iters"] / max(1, st["newton_solves"]),
+            "n_nonfinite": st["n_nonfinite"], "newton_tol": w.newton_tol}
+
+
 def run_c4(I, torch, precision):
     """One pass of the 8e6-vertex spiral (1000 steps of dt 0.01 ms, 4 nodes, 3
     sweeps, the diffusion input redrawn every 50 steps: 20 launches), with all
@@ -893,6 +930,9 @@ def main():
         print("[bench] serving trace: %d requests" % args.serving_requests, file=sys.stderr, flush=True)
         serving = serve.run_trace(W.c5_trace(n_requests=args.serving_requests), verbose=True)
 
+    print("[bench] C1 LR91 fp64, 4096 vertices x 1000 steps", file=sys.stderr, flush=True)
+    c1 = run_c1(I, torch)
+
     c4 = None
     if not args.no_c4:
         c4 = {}
@@ -955,6 +995,7 @@ def main():
         "roofline": m["roofline"],
         "t_min": m["t_min"],
         "microbench": micro,
+        "c1_lr91": c1,
         "c4_spiral": c4,
         "traffic_algorithmic_bytes": m["traffic_algorithmic_bytes"],
         "hbm_gbs_algorithmic": m["hbm_gbs_algorithmic"],

@@ -596,14 +596,9 @@ __global__ void __launch_bounds__(kBlock)
               static_for<N>([&](auto i) { Q(mm, i) += Sdt[mm][1] * double(f[i]); });
             });
           }
-          // in double the update starts from the copy xe (the same value), so
-          // X_{m+1} itself is dead during the evaluation
           static_for<N>([&](auto I) {
             constexpr int i = I;
-            if constexpr (!Prec::mixed)
-              L::template at<i>(X[m + 1]) = xe[i] + delta[i];
-            else
-              L::template at<i>(X[m + 1]) += delta[i];
+            L::template at<i>(X[m + 1]) += delta[i];
           });
         });
       }
