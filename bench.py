@@ -120,9 +120,9 @@ def write_traffic_file(fetch_csv, write_csv):
     lines = ["# HBM traffic of sdc_kernel<TT06, *, 3, Newton>, TT06 slab 1e6 vertices x 500 steps, "
              "per launch",
              "# commands (repository root, MI355X):",
-             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/final/fetch -o fetch -- "
+             "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fetch -o fetch -- "
              + short,
-             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/final/write -o write -- "
+             "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/write -o write -- "
              + short,
              "#   python3 bench.py --traffic-from <fetch csv> <write csv>",
              "# counters scaled by their reading for the state-restore copy (known bytes)",
