@@ -43,7 +43,7 @@ struct BlockArgs {
 };
 
 template <class Model>
-__global__ void __launch_bounds__(64) imp_block_kernel(const BlockArgs<Model> args) {
+__global__ void __launch_bounds__(64, 2) imp_block_kernel(const BlockArgs<Model> args) {
   constexpr int N = Model::N;
   const ImpBlock& a = args.a;
   const long long v = (long long)blockIdx.x * 64 + threadIdx.x;
