@@ -78,6 +78,22 @@ SHORT_FLAGS = ("--no-serving", "--no-cpu", "--no-ros2", "--no-rl", "--no-diffusi
                "--no-bidomain", "--no-c4", "--no-micro")
 
 
+def step_kernel_args(name):
+    """The template arguments of a step kernel's name in a rocprofv3 record,
+    e.g. 'sdc_kernel<ionic::TT06, ionic::Mixed, 3, 0, 1>' -> ['ionic::TT06',
+    'ionic::Mixed', '3', '0', '1'] (model, precision, nodes, predictor, and
+    wavefronts per SIMD where the name carries it); None for other kernels."""
+    if "sdc_kernel<" not in name:
+        return None
+    inner = name.split("sdc_kernel<", 1)[1].split(">", 1)[0]
+    return [a.strip() for a in inner.split(",")]
+
+
+def is_tt06_newton_step(name):
+    args = step_kernel_args(name)
+    return args is not None and "TT06" in args[0] and args[3] == "0"
+
+
 def traffic_from_counters(fetch_csv, write_csv):
     """HBM bytes per launch of the step kernels from two rocprofv3 --pmc runs
     (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) of `bench.py --steps 1 --warmup 0`.
@@ -91,9 +107,9 @@ def traffic_from_counters(fetch_csv, write_csv):
         for r in rows:
             v = float(r["Counter_Value"]) * 1024.0
             name = r["Kernel_Name"]
-            if "sdc_kernel" in name and "TT06" in name:
-                # the Newton kernels: predictor 0, the last template argument
-                if not name.split(">")[0].rstrip().endswith("0"):
+            if "sdc_kernel" in name:
+                # the TT06 Newton kernels (predictor 0)
+                if not is_tt06_newton_step(name):
                     continue
                 # the first dispatch of each precision: the Newton tol 1e-10 pass
                 kern.setdefault("fp64" if "Fp64" in name else "mixed", v)
@@ -469,8 +485,7 @@ def valu_mix(csv_paths, n_steps=500):
         seen = {}
         for r in csv.DictReader(open(path)):
             name = r["Kernel_Name"]
-            if ("sdc_kernel" not in name or "TT06" not in name
-                    or not name.split(">")[0].rstrip().endswith("0")):
+            if not is_tt06_newton_step(name):
                 continue
             prec = "fp64" if "Fp64" in name else "mixed"
             d = seen.setdefault(prec, r["Dispatch_Id"])

@@ -31,7 +31,17 @@ struct OpsImpl {
     a.state_alt = c.state_alt;
     for (int s = 0; s < kMaxBatch; ++s) a.sims[s] = c.sims[s];
     static_assert(sizeof(LaunchArgs<P>) <= 3800, "kernel arguments must fit the kernarg segment");
-    hipLaunchKernelGGL((sdc_kernel<Model, Prec, M, Pred>), dim3(blocks), dim3(kBlock), 0, st, a);
+    // the two-wavefront build only when the launch gives every SIMD two
+    // wavefronts (256 compute units x 4 SIMDs x 2)
+    constexpr int kTwoWaveBlocks = 2048;
+    if constexpr (StepPolicy<Model, Prec, M, Pred>::waves == 2) {
+      if (blocks >= kTwoWaveBlocks) {
+        hipLaunchKernelGGL((sdc_kernel<Model, Prec, M, Pred, 2>), dim3(blocks), dim3(kBlock), 0, st,
+                           a);
+        return hipGetLastError();
+      }
+    }
+    hipLaunchKernelGGL((sdc_kernel<Model, Prec, M, Pred, 1>), dim3(blocks), dim3(kBlock), 0, st, a);
     return hipGetLastError();
   }
 

@@ -329,6 +329,15 @@ struct StepPolicy {
   static constexpr bool lds = large && !Prec::mixed && (M == 3 || M == 4);
   static constexpr bool split_evals =
       large && (!Prec::mixed || (M >= 4 && Pred != 1 /* ROS2 */));
+  // wavefronts per SIMD a build for a full grid is held to: two (at most 256
+  // registers per lane, what spills there is going to scratch) where measured
+  // faster than one wavefront with 512 registers: LR91 with 2 and 3 nodes
+  // (10-23% on 1e6 vertices), TT06 mixed with 2 nodes and the ROS2 or
+  // Rush-Larsen predictor (4%, 12%); not TT06 mixed with 2 nodes and Newton (5%
+  // slower), nor LR91 mixed with 4 nodes (22% slower).  A launch too small to
+  // give every SIMD two wavefronts takes the one-wavefront build.
+  static constexpr int waves =
+      (!large && M <= 3) || (large && Prec::mixed && M == 2 && Pred != 0) ? 2 : 1;
 };
 
 // An opaque copy: the optimiser cannot relate the result to the argument.
@@ -337,8 +346,10 @@ IONIC_DEV void opaque(T (&x)[N]) {
   for (int q = 0; q < N; ++q) asm volatile("" : "+v"(x[q]));
 }
 
-template <class Model, class Prec, int M, int Pred>
-__global__ void __launch_bounds__(kBlock)
+// W: wavefronts per SIMD the build is held to (1: up to 512 registers per
+// lane; 2: up to 256)
+template <class Model, class Prec, int M, int Pred, int W>
+__global__ void __launch_bounds__(kBlock, W)
     sdc_kernel(const LaunchArgs<typename Model::template Params<typename Prec::TE>> args) {
   using L = Layout<Model, Prec>;
   using TE = typename Prec::TE;

@@ -36,9 +36,10 @@ def test_counters_scaled_by_the_state_restore_copies(tmp_path):
         _pmc_csv(tmp_path / (name + ".csv"), [
             ("__amd_rocclr_copyBuffer", f * fp64 / 1024), ("__amd_rocclr_copyBuffer", f * mixed / 1024),
             ("__amd_rocclr_copyBuffer", 10.0),                                   # too small: ignored
-            ("void ionic::sdc_kernel<ionic::TT06, ionic::Fp64, 3, 0>(ionic::LaunchArgs)", f * 3e9 / 1024),
-            ("void ionic::sdc_kernel<ionic::TT06, ionic::Mixed, 3, 0>(ionic::LaunchArgs)", f * 2e8 / 1024),
-            ("void ionic::sdc_kernel<ionic::TT06, ionic::Mixed, 2, 1>(ionic::LaunchArgs)", 1e9),  # ROS2: ignored
+            ("void ionic::sdc_kernel<ionic::TT06, ionic::Fp64, 3, 0, 1>(ionic::LaunchArgs)", f * 3e9 / 1024),
+            ("void ionic::sdc_kernel<ionic::TT06, ionic::Mixed, 3, 0, 1>(ionic::LaunchArgs)", f * 2e8 / 1024),
+            ("void ionic::sdc_kernel<ionic::TT06, ionic::Mixed, 2, 1, 2>(ionic::LaunchArgs)", 1e9),  # ROS2: ignored
+            ("void ionic::sdc_kernel<ionic::LR91, ionic::Fp64, 3, 0, 2>(ionic::LaunchArgs)", 1e9),  # LR91: ignored
         ])
     t = bench.traffic_from_counters(tmp_path / "fetch.csv", tmp_path / "write.csv")
     assert t["fp64"]["fetch"] == pytest.approx(3e9) and t["fp64"]["write"] == pytest.approx(3e9)
@@ -58,3 +59,12 @@ def test_traffic_reported_only_for_the_recorded_sources(tmp_path, monkeypatch):
     assert bench.read_traffic("mixed") is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
     assert bench.read_traffic("mixed") is None
+
+
+def test_step_kernel_names():
+    assert bench.step_kernel_args("void ionic::sdc_kernel<ionic::TT06, ionic::Mixed, 3, 0, 1>(x)") == [
+        "ionic::TT06", "ionic::Mixed", "3", "0", "1"]
+    assert bench.is_tt06_newton_step("void ionic::sdc_kernel<ionic::TT06, ionic::Fp64, 3, 0>(x)")
+    assert not bench.is_tt06_newton_step("void ionic::sdc_kernel<ionic::TT06, ionic::Mixed, 2, 1, 2>(x)")
+    assert not bench.is_tt06_newton_step("void ionic::sdc_kernel<ionic::LR91, ionic::Fp64, 3, 0, 2>(x)")
+    assert bench.step_kernel_args("ionic::cg_q_kernel(ionic::CgParams)") is None
