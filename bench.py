@@ -845,9 +845,9 @@ def main():
         trace_overlap(args.trace_overlap, args.trace_skip)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the reaction stage shards by vertex ranges with no "
-              "exchange, and this build runs and reports a single MI355X only (--gpus 1).",
-              file=sys.stderr)
+        print("bench.py measures one GPU (--gpus 1): the reaction stage would shard by vertex "
+              "ranges with no exchange, and only the single-MI355X figures are measured and "
+              "reported.", file=sys.stderr)
         sys.exit(2)
 
     import torch
