@@ -8,7 +8,10 @@ serves) together: each round launches one batched kernel per class over a
 chunk of steps (reaction_sdc_step_batch), on one stream per class so the
 classes overlap on the GPU.  A chunk is at least chunk_steps steps and at least
 quantum_vertices * chunk_steps vertex-steps, so a small request finishes in
-one round instead of waiting out as many rounds as a large one.  Between chunks it retires finished requests
+one round instead of waiting out as many rounds as a large one; with
+split_small, requests below quantum_vertices form classes (and streams) of
+their own, so a new small request does not wait for the round of the large
+ones of its kind.  Between chunks it retires finished requests
 (their final V is copied to the host) and admits arrivals in FIFO order while
 the resident footprint stays within the HBM budget and a slot is free; neither
 step waits for the device.  A request computes exactly what it computes alone:
@@ -115,8 +118,9 @@ class Result:
 class Server:
     budget_bytes: float = 200e9
     slots: int = 128
-    chunk_steps: int = 50
-    quantum_vertices: int = 400_000     # jobs below this many vertices take longer chunks
+    chunk_steps: int = 25
+    quantum_vertices: int = 1_000_000   # jobs below this many vertices take longer chunks
+    split_small: bool = True            # small jobs (below quantum_vertices) get streams of their own
     keep_state: bool = False            # keep each result's full state (tests)
     results: List[Result] = field(default_factory=list)
     rejected: List[int] = field(default_factory=list)
@@ -238,7 +242,8 @@ class Server:
             adm, rej = policy.take(waiting, lambda r: r.footprint_bytes())
             self.rejected += [r.rid for r in rej]
             for req in adm:
-                cls = (req.model, req.precision, req.n_nodes)
+                cls = (req.model, req.precision, req.n_nodes,
+                       bool(self.split_small and req.n < self.quantum_vertices))
                 if cls not in streams:
                     streams[cls] = torch.cuda.Stream()
                 active.setdefault(cls, []).append(start(req))

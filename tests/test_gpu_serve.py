@@ -30,7 +30,7 @@ def small_trace():
 
 def test_results_in_the_mix_equal_results_alone():
     trace = small_trace()
-    srv = Server(chunk_steps=16, quantum_vertices=1000, slots=6, keep_state=True)
+    srv = Server(chunk_steps=16, quantum_vertices=1000, split_small=True, slots=6, keep_state=True)
     res = {r.rid: r for r in srv.run(trace)}
     say("serving summary", summarize(list(res.values())))
     assert len(res) == len(trace)
