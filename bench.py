@@ -239,10 +239,23 @@ def state_bytes_per_vertex(precision):
     return 19 * 8 if precision == "fp64" else 6 * 8 + 13 * 4
 
 
+VERTEX_ORDER = ("4 x 4 x 4 blocks of the grid per wavefront in the mixed kernels "
+                "(ionic_set_vertex_order)")
+
+
+def grid_order(sim, w):
+    """The slab and spiral runs process their vertices in 4 x 4 x 4 blocks of the
+    grid per wavefront; the results are the same bit for bit in any order."""
+    from paper_2510_27447_amd import workloads as W
+    if len(w.grid) == 3:
+        sim.set_vertex_order(W.blocked_order(*w.grid))
+
+
 def run_pass_set(I, torch, w, steps, warmup, predictor="newton", sample=None, rates=None):
     sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
                        newton_maxit=w.newton_maxit)
     sim.set_predictor(predictor)
+    grid_order(sim, w)
     stim = torch.as_tensor(w.i_stim).cuda()
     diff = torch.as_tensor(w.i_diff).cuda()
     init = sim.state.clone()
@@ -331,6 +344,7 @@ def run_adaptive(I, torch, w, err_tol, t_end, dt_max, dt_init=0.01):
     ROS2 predictor, 2 nodes, 1 correction, one step size for all vertices.
     One untimed run, then one timed run from the same initial state."""
     sim = I.Simulation(w.model, w.x0, precision=w.precision)
+    grid_order(sim, w)
     stim = torch.as_tensor(w.i_stim).cuda()
     diff = torch.as_tensor(w.i_diff).cuda()
     init = sim.state.clone()
@@ -376,6 +390,7 @@ def run_reaction_diffusion(I, torch, w, steps, warmup, h=0.01, sigma=0.75e-3):
     2 ms.  Also times the diffusion kernel alone."""
     sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
                        newton_maxit=w.newton_maxit)
+    grid_order(sim, w)
     # a one-plane stimulus drains into the tissue; five planes start a planar wave
     stim_np = np.where(np.arange(w.n) % w.grid[0] < 5, -100.0, 0.0)
     stim = torch.as_tensor(stim_np).cuda()
@@ -439,6 +454,7 @@ def run_bidomain(I, torch, w, n_steps=100, rtol=1e-8, max_iter=2000, h=0.01, sig
     time of one CG iteration from 100 iterations at rtol 0."""
     sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
                        newton_maxit=w.newton_maxit)
+    grid_order(sim, w)
     stim = torch.as_tensor(np.where(np.arange(w.n) % w.grid[0] < 5, -100.0, 0.0)).cuda()
     grid = I.make_bidomain_grid(*w.grid, h=h, sigma_i=(sigma,) * 3, sigma_e=(sigma,) * 3)
     wb = I.ionic_elliptic_work_bytes(*w.grid, max_iter)
@@ -777,6 +793,7 @@ def run_c4(I, torch, precision):
     w = W.c4_tt06_spiral(precision=precision)
     sim = I.Simulation(w.model, w.x0, precision=w.precision, newton_tol=w.newton_tol,
                        newton_maxit=w.newton_maxit)
+    grid_order(sim, w)
     I.ionic_gates_to_steady_state(sim.handle)
     diffs = [torch.as_tensor(d).cuda() for d in w.i_diff_series]
     n, n_steps = w.n, w.n_steps
@@ -994,7 +1011,7 @@ def main():
                         "(the mixed path stops at max(tol, 1e-6)); value = mixed precision (fp32 "
                         "F/J/solve, fp64 V/Ca/Na/K/residual); fp64 alongside at 1e-10 and 1e-6",
             "n_vertices": 1_000_000, "steps_per_pass": 500, "dt_ms": 0.02, "nodes": 3, "sweeps": 3,
-            "seed": 0,
+            "seed": 0, "vertex_order": VERTEX_ORDER,
         },
         "kernel_ms": m["kernel_ms"],
         "newton_tol": m["newton_tol"],

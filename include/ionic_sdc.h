@@ -259,6 +259,26 @@ int reaction_sdc_step(ionic_sim* sim, double t0, double dt, int n_steps, int n_n
  * Host only; takes effect for work enqueued afterwards. */
 int ionic_set_predictor(ionic_sim* sim, int predictor);
 
+/* Processing order of the vertices in the mixed-precision step kernels
+ * (reaction_sdc_step, reaction_sdc_step_batch, reaction_sdc_adaptive, and the
+ * reaction steps of the diffusion and bidomain entries): lane slot k of the
+ * launch advances vertex order_dev[k].  Every vertex computes exactly what it
+ * computes in any other order (bit for bit) and the state stays in the
+ * caller's vertex order in HBM; the order only decides which vertices share a
+ * wavefront, and with it how far their Newton iteration counts differ (a
+ * wavefront iterates until its last lane has converged).  On a structured
+ * grid, blocks of 4 x 4 x 4 neighbouring vertices per wavefront keep a
+ * depolarisation front inside few wavefronts.  IONIC_FP64 handles accept and
+ * check the order but keep the identity mapping (no measurable gain there,
+ * and the double kernels have no registers to spare for it); their results
+ * are the same either way.
+ *   order_dev: n int32 on the device, a permutation of [0, n) (checked here:
+ *              copied to the host once; IONIC_EINVAL otherwise), caller-owned,
+ *              read by every later launch, so it must outlive them; NULL
+ *              restores the identity order.  n must equal the handle's vertex
+ *              count.  Synchronises the device copy. */
+int ionic_set_vertex_order(ionic_sim* sim, const int32_t* order_dev, int64_t n);
+
 /* Adaptive time stepping from t0 to t_end with the ROS2 predictor and
  * n_sweeps corrections on n_nodes nodes (the paper's scheme: n_nodes = 2,
  * n_sweeps = 1), one step size for all vertices (section 3.3.1: the embedded

@@ -187,6 +187,7 @@ struct ionic_sim {
   const double* i_stim = nullptr;
   const double* i_diff = nullptr;
   long long step_offset = 0;
+  const int32_t* order = nullptr;  // vertex processing order (device, caller-owned) or null
   // multigrid tables of the last bidomain grid (the coarsest inverse costs
   // O(n^3) on the host, so it is formed once per grid and conductivities)
   long long mg_dims[3] = {0, 0, 0};
@@ -247,6 +248,7 @@ SimDesc desc_of(const ionic_sim* s, double t0, double dt, const double* stim, do
   d.n_steps = n_steps;
   d.n_sweeps = K;
   d.stats = s->stats;
+  d.order = s->order;
   d.first_block = first_block;
   return d;
 }
@@ -1023,6 +1025,29 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
   IONIC_HIP(hipStreamSynchronize(st));
   acc.cg_iterations = ell.cg_iterations;
   if (info) *info = acc;
+  return IONIC_OK;
+}
+
+int ionic_set_vertex_order(ionic_sim* s, const int32_t* order_dev, int64_t n) {
+  if (!s) return fail(IONIC_EINVAL, "sim is NULL");
+  if (!order_dev) {
+    s->order = nullptr;
+    return IONIC_OK;
+  }
+  if (n != s->n) return fail(IONIC_EINVAL, "order must hold one entry per vertex");
+  // a non-permutation would make lanes share or leave vertices, an index out of
+  // range would read outside the state: check the caller's array once, here
+  std::vector<int32_t> h(static_cast<size_t>(n));
+  IONIC_HIP(hipMemcpy(h.data(), order_dev, sizeof(int32_t) * size_t(n), hipMemcpyDeviceToHost));
+  std::vector<unsigned char> seen(static_cast<size_t>(n), 0);
+  for (int64_t i = 0; i < n; ++i) {
+    const int32_t v = h[size_t(i)];
+    if (v < 0 || int64_t(v) >= n || seen[size_t(v)])
+      return fail(IONIC_EINVAL, "order is not a permutation of the vertices (entry " +
+                                    std::to_string(i) + ")");
+    seen[size_t(v)] = 1;
+  }
+  s->order = order_dev;
   return IONIC_OK;
 }
 

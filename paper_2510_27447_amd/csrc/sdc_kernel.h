@@ -108,6 +108,7 @@ struct SimDesc {
   long long step_offset;   // steps already taken from t0
   int n_steps, n_sweeps;
   DevStats* stats;         // kSlots slots
+  const int* order;        // vertex advanced by each lane slot (a permutation of [0, n)) or null
   int first_block;         // first workgroup of this simulation in the launch
   int pad;
 };
@@ -363,7 +364,12 @@ __global__ void __launch_bounds__(kBlock, W)
   const SimDesc& sd = args.sims[sidx];
   const long long v = (long long)(blockIdx.x - sd.first_block) * kBlock + threadIdx.x;
   const bool active = v < sd.n;
-  const long long vi = active ? v : sd.n - 1;  // tail lanes shadow the last vertex
+  const long long vc = active ? v : sd.n - 1;  // tail lanes shadow the last slot
+  // the vertex this lane advances (every lane reads and writes its own vertex
+  // only).  Only the mixed kernels take the processing order: it made no
+  // difference to the double ones, whose registers it crowded (spills)
+  constexpr bool kOrdered = Prec::mixed;
+  const long long vi = (kOrdered && sd.order) ? (long long)sd.order[vc] : vc;
 
   double t0 = sd.t0, dt = sd.dt;
   const void* src = sd.state;
@@ -622,7 +628,14 @@ __global__ void __launch_bounds__(kBlock, W)
     constexpr int i = I;
     if (!isfinite(double(L::template at<i>(X[0])))) nonfinite = 1;
   });
-  if (active) L::store(X[0], dst, sd.stride, v);
+  if constexpr (kOrdered) {
+    // the vertex index is read again for the store (a volatile read, so the
+    // compiler does not keep it in registers through the whole step loop)
+    const long long vs = sd.order ? (long long)*(const volatile int*)(sd.order + vc) : vc;
+    if (active) L::store(X[0], dst, sd.stride, vs);
+  } else {
+    if (active) L::store(X[0], dst, sd.stride, v);
+  }
 
   if constexpr (Pred == kPredRos2) {
     if (args.ctl) {  // largest lane error of the attempt; a non-finite state rejects it

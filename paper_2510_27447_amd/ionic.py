@@ -119,6 +119,7 @@ _SIGNATURES = {
     "reaction_sdc_step": (c_int, [c_void_p, c_double, c_double, c_int, c_int, c_int, c_void_p,
                                   c_double, c_double, c_void_p, c_void_p]),
     "ionic_set_predictor": (c_int, [c_void_p, c_int]),
+    "ionic_set_vertex_order": (c_int, [c_void_p, c_void_p, c_int64]),
     "reaction_sdc_adaptive": (c_int, [c_void_p, c_double, c_double, c_double, c_double, c_double,
                                       c_int, c_int, c_void_p, c_double, c_double, c_void_p,
                                       c_void_p, c_size_t, c_int64, c_void_p,
@@ -295,6 +296,18 @@ def ionic_set_predictor(handle, predictor):
     _check(lib().ionic_set_predictor(handle, PREDICTORS.get(predictor, predictor)))
 
 
+def ionic_set_vertex_order(handle, order, n):
+    """order: a device int32 tensor holding a permutation of range(n), kept alive
+    by the caller while the handle steps, or None for the identity order."""
+    import torch
+    if order is None:
+        _check(lib().ionic_set_vertex_order(handle, None, 0))
+        return
+    if order.dtype != torch.int32 or not order.is_cuda or not order.is_contiguous():
+        raise ValueError("order must be a contiguous int32 device tensor")
+    _check(lib().ionic_set_vertex_order(handle, c_void_p(order.data_ptr()), int(order.numel())))
+
+
 def reaction_sdc_adaptive(handle, t0, t_end, dt_init, dt_max, err_tol, n_nodes, n_sweeps,
                           work, work_bytes, max_attempts, i_stim=None, stim_t_on=0.0,
                           stim_t_off=0.0, i_diff=None, history=None, stream=None):
@@ -464,6 +477,18 @@ class Simulation:
 
     def set_predictor(self, predictor):
         ionic_set_predictor(self.handle, predictor)
+
+    def set_vertex_order(self, order):
+        """order: a permutation of range(n) (numpy or device tensor) or None."""
+        import torch
+        if order is None:
+            self._order = None
+            ionic_set_vertex_order(self.handle, None, 0)
+            return
+        t = torch.as_tensor(np.ascontiguousarray(order, dtype=np.int32)).cuda() \
+            if not isinstance(order, torch.Tensor) else order
+        ionic_set_vertex_order(self.handle, t, self.n)
+        self._order = t   # the library reads it on every later launch
 
     def adaptive(self, t0, t_end, dt_init, dt_max, err_tol, n_nodes=2, n_sweeps=1, i_stim=None,
                  stim_t_on=0.0, stim_t_off=0.0, i_diff=None, max_attempts=100000,

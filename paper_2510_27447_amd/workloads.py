@@ -89,6 +89,17 @@ class Workload:
                         self.steady_gates, self.seed, ())
 
 
+def blocked_order(nx, ny, nz, b=4):
+    """A processing order of a structured grid's vertices (index i + nx (j + ny k))
+    in which each run of b^3 consecutive entries is a b x b x b block of
+    neighbouring vertices (partial blocks at the far faces), for
+    ionic_set_vertex_order: a wavefront of 64 lanes then holds one 4 x 4 x 4 block."""
+    idx = np.arange(nx * ny * nz, dtype=np.int64).reshape(nz, ny, nx)
+    parts = [idx[k:k + b, j:j + b, i:i + b].ravel()
+             for k in range(0, nz, b) for j in range(0, ny, b) for i in range(0, nx, b)]
+    return np.concatenate(parts).astype(np.int32)
+
+
 def c1_lr91(seed=0, nx=64, ny=64, n_steps=1000):
     rng = np.random.Generator(np.random.PCG64(seed))
     N = nx * ny
