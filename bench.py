@@ -863,7 +863,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU (--gpus 1): the reaction stage would shard by vertex "
-              "ranges with no exchange, and only the single-MI355X figures are measured and "
+              "ranges with no exchange, and only figures on a single MI355X are measured and "
               "reported.", file=sys.stderr)
         sys.exit(2)
 
