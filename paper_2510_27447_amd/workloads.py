@@ -89,14 +89,17 @@ class Workload:
                         self.steady_gates, self.seed, ())
 
 
-def blocked_order(nx, ny, nz, b=4):
+def blocked_order(nx, ny, nz, b=4, by=None, bz=None):
     """A processing order of a structured grid's vertices (index i + nx (j + ny k))
-    in which each run of b^3 consecutive entries is a b x b x b block of
-    neighbouring vertices (partial blocks at the far faces), for
-    ionic_set_vertex_order: a wavefront of 64 lanes then holds one 4 x 4 x 4 block."""
+    in which each run of b * by * bz consecutive entries is a block of b x by x bz
+    neighbouring vertices, x fastest inside a block (partial blocks at the far
+    faces), for ionic_set_vertex_order; by and bz default to b, so that a
+    wavefront of 64 lanes holds one 4 x 4 x 4 block."""
+    by = b if by is None else by
+    bz = b if bz is None else bz
     idx = np.arange(nx * ny * nz, dtype=np.int64).reshape(nz, ny, nx)
-    parts = [idx[k:k + b, j:j + b, i:i + b].ravel()
-             for k in range(0, nz, b) for j in range(0, ny, b) for i in range(0, nx, b)]
+    parts = [idx[k:k + bz, j:j + by, i:i + b].ravel()
+             for k in range(0, nz, bz) for j in range(0, ny, by) for i in range(0, nx, b)]
     return np.concatenate(parts).astype(np.int32)
 
 
