@@ -280,6 +280,96 @@ IONIC_DEV void eval_solve(const typename Model::template Params<T>& p, T stim, T
   static_for<Model::N>([&](auto I) { f[I] = s.f[I]; });
 }
 
+// F and J rows held for a later solve at the same point: row i's value, then
+// its partials on the pattern ROW[i] (zero where the evaluation carried none),
+// one word each, in one column per lane of a [words][kBlock] array.
+template <class Model>
+struct JacRows {
+  static constexpr int N = Model::N;
+  static constexpr int off(int i) {
+    int o = 0;
+    for (int j = 0; j < i; ++j) o += 1 + popc(Model::ROW[j]);
+    return o;
+  }
+  static constexpr int kWords = off(N);
+};
+
+// Passes every row on to the inner sink and keeps a copy in a JacRows column.
+template <class Model, class T, class Inner>
+struct SinkRecord {
+  Inner& in;
+  T* col;  // this lane's column: word w at col[w * kBlock]
+  bool rec;
+  template <int i, uint32_t Mx>
+  IONIC_DEV void put(const D<T, Mx>& x) {
+    constexpr int o = JacRows<Model>::off(i);
+    if (rec) {
+    col[o * kBlock] = x.v;
+    for_bits<Model::ROW[i]>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (has(Mx, k))
+        col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = x.template d<k>();
+      else
+        col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = T(0);
+    });
+    }
+    in.template put<i>(x);
+  }
+};
+
+// Keeps the rows in a JacRows column only.
+template <class Model, class T>
+struct SinkKeep {
+  T* col;
+  template <int i, uint32_t Mx>
+  IONIC_DEV void put(const D<T, Mx>& x) {
+    constexpr int o = JacRows<Model>::off(i);
+    col[o * kBlock] = x.v;
+    for_bits<Model::ROW[i]>([&](auto K) {
+      constexpr int k = K;
+      if constexpr (has(Mx, k))
+        col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = x.template d<k>();
+      else
+        col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = T(0);
+    });
+  }
+};
+
+// eval_solve that also keeps the F and J rows in a JacRows column
+template <class Model, class T, class BFn>
+IONIC_DEV void eval_solve_keep(const typename Model::template Params<T>& p, T stim, T diff, T dtau,
+                               const T (&x)[Model::N], BFn bfn, T (&f)[Model::N],
+                               T (&delta)[Model::N], T* col, bool rec) {
+  SinkElim<Model, T, BFn> s(dtau, bfn);
+  SinkRecord<Model, T, SinkElim<Model, T, BFn>> r{s, col, rec};
+  call_rhs_FJ<Model, T>(p, stim, diff, r, x, std::make_index_sequence<Model::N>{});
+  s.solve(delta);
+  static_for<Model::N>([&](auto I) { f[I] = s.f[I]; });
+}
+
+// The solve of eval_solve from rows kept by eval_solve_keep at the same point
+// (any dtau and right-hand side): the rows are fed to the elimination again,
+// rows eliminated first before the core rows, as the model emits them.
+template <class Model, class T, class BFn>
+IONIC_DEV void replay_solve(T dtau, BFn bfn, T (&f)[Model::N], T (&delta)[Model::N],
+                            const T* col) {
+  using E = Elim<Model>;
+  SinkElim<Model, T, BFn> s(dtau, bfn);
+  __builtin_amdgcn_sched_barrier(0);
+  static_for<Model::N>([&](auto K) {
+    constexpr int i = E::at(K);
+    constexpr uint32_t R = Model::ROW[i];
+    constexpr int o = JacRows<Model>::off(i);
+    D<T, R> x;
+    x.v = col[o * kBlock];
+    static_for<popc(R)>([&](auto J) { x.g[J] = col[(o + 1 + J) * kBlock]; });
+    s.template put<i>(x);
+  });
+  __builtin_amdgcn_sched_barrier(0);
+  s.solve(delta);
+  static_for<Model::N>([&](auto I) { f[I] = s.f[I]; });
+}
+
 IONIC_DEV unsigned long long wave_sum(unsigned long long x) {
   for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
   return x;
@@ -339,6 +429,22 @@ struct StepPolicy {
   // give every SIMD two wavefronts takes the one-wavefront build.
   static constexpr int waves =
       (!large && M <= 3) || (large && Prec::mixed && M == 2 && Pred != 0) ? 2 : 1;
+  // reuse: the first Newton iteration on sub-interval 1 starts at X_1, the
+  // node the first sweep's solve at node 1 evaluates F and J at; its rows
+  // are kept in LDS (JacRows: 95 words per lane for TT06, 32 for LR91) and
+  // that solve is replayed from them (with its own dtau and right-hand side)
+  // instead of evaluating the model again: one evaluation per step fewer.
+  // Where the evaluation at node 1 is still made (later sweeps) its rows go
+  // through LDS the same way, so the solve is one code path.  Used by the
+  // mixed kernels where it measured faster on 1e6 vertices: LR91 with 3
+  // nodes (60.0 -> 54.5 ms for 500 steps), TT06 with 4 nodes (191 -> 187 ms
+  // for 200 steps) and 5 (279 -> 213 ms for 100 steps; fewer spills).  Not
+  // kept: TT06 mixed with 3 nodes (the kernel then spills, 0 -> 168 B per
+  // lane, 234 -> 261 ms), LR91 mixed with 4 nodes (81 -> 86 ms), the LR91
+  // double kernels (the same or slower); the TT06 double kernels' rows would
+  // double the LDS a workgroup holds.
+  static constexpr bool reuse =
+      Pred == 0 && Prec::mixed && (large ? M >= 4 : M == 3);
 };
 
 // An opaque copy: the optimiser cannot relate the result to the argument.
@@ -405,6 +511,9 @@ __global__ void __launch_bounds__(kBlock, W)
   using Pol = StepPolicy<Model, Prec, M, Pred>;
   __shared__ TE lds_f0[Pol::lds ? N : 1][kBlock];
   __shared__ double lds_q[Pol::lds ? (M - 1) * N : 1][kBlock];
+  // F and J rows at X_1 from the predictor, for the first sweep (Pol::reuse)
+  __shared__ TE lds_jac[Pol::reuse ? JacRows<Model>::kWords : 1][kBlock];
+  TE* const jac_col = &lds_jac[0][threadIdx.x];
   TE reg_f0[Pol::lds ? 1 : N];
   double reg_q[Pol::lds ? 1 : (M - 1) * N];
   auto F0 = [&](int i) -> TE& {
@@ -536,7 +645,13 @@ __global__ void __launch_bounds__(kBlock, W)
             return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
                       double(dtau[m]) * double(fi));
           };
-          eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
+          if constexpr (Pol::reuse && m == 1) {
+            // the first iteration evaluates at Y = X_1: its rows serve the
+            // first sweep's solve at node 1 (pass is uniform over the wave)
+            eval_solve_keep<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta, jac_col, pass == 0);
+          } else {
+            eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
+          }
           // the first iteration on the first sub-interval evaluates at Y = X_n:
           // its F is the F(X_n) the sweeps need (pass counts the wave's
           // iterations, so this branch is uniform)
@@ -606,7 +721,18 @@ __global__ void __launch_bounds__(kBlock, W)
             if constexpr (m == 0) r += Sdt[0][1] * double(fi);
             return TE(r);
           };
-          eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
+          if constexpr (Pol::reuse && m == 0) {
+            // the first sweep solves at X_1, where the predictor kept F and J;
+            // a later sweep evaluates at the corrected node and keeps its rows
+            // the same way (k is uniform), so the solve is one code path
+            if (k > 0) {
+              SinkKeep<Model, TE> sk{jac_col};
+              call_rhs_FJ<Model, TE>(p, stim, diff, sk, xe, std::make_index_sequence<N>{});
+            }
+            replay_solve<Model, TE>(dtau[m], bfn, f, delta, jac_col);
+          } else {
+            eval_solve<Model, TE>(p, stim, diff, dtau[m], xe, bfn, f, delta);
+          }
           if constexpr (m == 0) {
             static_for<M - 2>([&](auto MM2) {
               constexpr int mm = MM2 + 1;

@@ -44,8 +44,11 @@ def test_fp64_matches_oracle(model, M, K):
     assert st["newton_solves"] == w.n * w.n_steps * (M - 1)
 
 
+# (3, 1), (4, 1), (5, 2), (4, 0): the kernels that take the predictor's F and
+# J at node 1 into the first sweep (LR91 with 3 nodes, TT06 with 4 and 5),
+# with one sweep only, with later sweeps, and with none
 @pytest.mark.parametrize("model", ["LR91", "TT06"])
-@pytest.mark.parametrize("M,K", [(2, 1), (3, 2), (3, 3), (4, 3)])
+@pytest.mark.parametrize("M,K", [(2, 1), (3, 2), (3, 3), (4, 3), (3, 1), (4, 1), (5, 2), (4, 0)])
 def test_mixed_matches_fp64_oracle(model, M, K):
     w = small_workload(model, "mixed", M, K)
     say("case", w.name)
