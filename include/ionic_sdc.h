@@ -60,9 +60,8 @@ extern "C" {
 enum { IONIC_LR91 = 1, IONIC_TT06_EPI = 2, IONIC_TEST_LINEAR = 90, IONIC_TEST_LOGISTIC = 91 };
 
 /* IONIC_FP64: everything in double.  IONIC_MIXED: F, J and the sparse solve
- * in float; V and the intracellular concentrations with their residuals,
- * quadrature sums and updates in double; the gates (TT06: also fCass and
- * Rbar) stored and updated, and their residuals and sums formed, in float. */
+ * in float; V, the intracellular concentrations, the SDC residual and their
+ * updates in double; gates stored and updated in float. */
 enum { IONIC_FP64 = 0, IONIC_MIXED = 1 };
 
 enum {
