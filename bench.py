@@ -206,9 +206,9 @@ def work_split(vertex_steps, M, K, newton_iters, precision, ev=TT06_FLOPS, kinds
     count one each).  Mixed path: Wtr = every exp, log, expm1, sqrt,
     division and pivot reciprocal of the fp32 evaluations and solves (each one
     hardware transcendental instruction), W32 = their adds and multiplies,
-    W64 = the Newton residuals, the SDC quadrature and residuals and the
-    updates of the n64 double-held states (formed in double); the same work
-    for the fp32-held states and the stop tests are W32."""
+    W64 = the Newton residuals and the SDC quadrature and residuals (formed in
+    double) and the updates of the n64 double-held states; the updates of the
+    fp32 states and the stop tests are W32."""
     F_evals = vertex_steps * K * (M - 2)
     FJ_evals = newton_iters + vertex_steps * K * (M - 1)
     solve_rcp = n
@@ -222,11 +222,9 @@ def work_split(vertex_steps, M, K, newton_iters, precision, ev=TT06_FLOPS, kinds
     tr = lambda c: c["exp"] + c["log"] + c["expm1"] + c["sqrt"] + c["div"]
     ar = lambda c: c["add"] + c["mul"]
     wtr = F_evals * tr(kinds["F"]) + FJ_evals * (tr(kinds["FJ"]) + solve_rcp)
-    n32 = n - n64
     w32 = (F_evals * ar(kinds["F"]) + FJ_evals * (ar(kinds["FJ"]) + solve_arith)
-           + newton_iters * (2 * n + n32) + sw_nodes * n32
-           + newton_iters * 3 * n32 + sw_nodes * (2 * M + 2) * n32)
-    w64 = newton_iters * (3 * n64 + n64) + sw_nodes * ((2 * M + 2) * n64 + n64)
+           + newton_iters * (2 * n + (n - n64)) + sw_nodes * (n - n64))
+    w64 = newton_iters * (3 * n + n64) + sw_nodes * ((2 * M + 2) * n + n64)
     return {"W64": w64, "W32": w32, "Wtr": wtr}
 
 

@@ -30,9 +30,8 @@
 //
 // Precision policies: Fp64 evaluates F, J and the solve in double.  Mixed
 // evaluates them in float and keeps the first N64 states (V and the
-// intracellular concentrations) with their residuals and quadrature sums in
-// double; the other states are stored and updated, and their residuals and
-// sums formed, in float.
+// intracellular concentrations), the residuals and the quadrature in double;
+// the other states are stored and updated in float.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -238,13 +237,6 @@ struct Layout {
   }
 };
 
-// The type a state's residual and quadrature sums are formed in: double for
-// the states held in double, the evaluation type for the others (in the mixed
-// layout the float-held states' residuals and sums are rounded to float when
-// stored anyway).
-template <class L, int i>
-using ResT = std::conditional_t<(i < L::N64), double, typename L::TE>;
-
 template <class Model, class T, class Sink, size_t... I>
 IONIC_DEV void call_rhs_F(const typename Model::template Params<T>& p, T stim, T diff, Sink& s,
                           const T (&x)[Model::N], std::index_sequence<I...>) {
@@ -445,11 +437,12 @@ struct StepPolicy {
   // Where the evaluation at node 1 is still made (later sweeps) its rows go
   // through LDS the same way, so the solve is one code path.  Used by the
   // mixed kernels where it measured faster on 1e6 vertices: LR91 with 3
-  // nodes, TT06 with 4 and 5 (whose spills it also cuts).  Not kept: TT06
-  // mixed with 3 nodes (its sweep holds the merged F / F+J evaluation at node
-  // 2 across node 1's solve; 6% slower with the rows), LR91 mixed with 4
-  // nodes (6% slower), the LR91 double kernels (no faster); the TT06 double
-  // kernels' rows would double the LDS a workgroup holds.
+  // nodes (60.0 -> 54.5 ms for 500 steps), TT06 with 4 nodes (191 -> 187 ms
+  // for 200 steps) and 5 (279 -> 213 ms for 100 steps; fewer spills).  Not
+  // kept: TT06 mixed with 3 nodes (the kernel then spills, 0 -> 168 B per
+  // lane, 234 -> 261 ms), LR91 mixed with 4 nodes (81 -> 86 ms), the LR91
+  // double kernels (the same or slower); the TT06 double kernels' rows would
+  // double the LDS a workgroup holds.
   static constexpr bool reuse =
       Pred == 0 && Prec::mixed && (large ? M >= 4 : M == 3);
 };
@@ -505,21 +498,10 @@ __global__ void __launch_bounds__(kBlock, W)
   const TE diff = sd.i_diff ? TE(sd.i_diff[vi]) : TE(0);
   TE dtau[M - 1];
   double Sdt[M - 1][M];
-  TE SdtE[Prec::mixed ? M - 1 : 1][M];
   static_for<M - 1>([&](auto m) {
     dtau[m] = TE(args.dc[m] * dt);
-    static_for<M>([&](auto j) {
-      Sdt[m][j] = args.S[m][j] * dt;
-      if constexpr (Prec::mixed) SdtE[m][j] = TE(Sdt[m][j]);
-    });
+    static_for<M>([&](auto j) { Sdt[m][j] = args.S[m][j] * dt; });
   });
-  // S_mj dt in the residual type of state I
-  auto Sd = [&](int m, int j, auto I) -> ResT<L, decltype(I)::value> {
-    if constexpr (decltype(I)::value < L::N64)
-      return Sdt[m][j];
-    else
-      return SdtE[m][j];
-  };
   const TE tol = TE(args.tol);
 
   Node X[M];
@@ -533,23 +515,18 @@ __global__ void __launch_bounds__(kBlock, W)
   __shared__ TE lds_jac[Pol::reuse ? JacRows<Model>::kWords : 1][kBlock];
   TE* const jac_col = &lds_jac[0][threadIdx.x];
   TE reg_f0[Pol::lds ? 1 : N];
-  double reg_q[Pol::lds ? 1 : (M - 1) * L::N64];
-  TE reg_q32[(Pol::lds || L::N32 == 0) ? 1 : (M - 1) * L::N32];
+  double reg_q[Pol::lds ? 1 : (M - 1) * N];
   auto F0 = [&](int i) -> TE& {
     if constexpr (Pol::lds)
       return lds_f0[i][threadIdx.x];
     else
       return reg_f0[i];
   };
-  // Q_m of state I, in that state's residual type
-  auto Q = [&](int m, auto I) -> ResT<L, decltype(I)::value>& {
-    constexpr int i = decltype(I)::value;
+  auto Q = [&](int m, int i) -> double& {
     if constexpr (Pol::lds)
       return lds_q[m * N + i][threadIdx.x];
-    else if constexpr (i < L::N64)
-      return reg_q[m * L::N64 + i];
     else
-      return reg_q32[m * L::N32 + (i - L::N64)];
+      return reg_q[m * N + i];
   };
 
   unsigned long long it_total = 0;
@@ -623,8 +600,8 @@ __global__ void __launch_bounds__(kBlock, W)
           // core rows: b = -(Y - X_m - dtau F(Y)), formed in double
           auto bfn = [&](auto I, TE fi) -> TE {
             constexpr int i = I;
-            using R = ResT<L, i>;
-            return TE(R(L::template at<i>(X[m])) - R(L::template at<i>(Y)) + R(dtau[m]) * R(fi));
+            return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
+                      double(dtau[m]) * double(fi));
           };
           SinkCore<Model, TE, decltype(bfn)> s(dtau[m], bfn);
           call_rhs_masked<Model, TE, CORE>(p, stim, diff, s, xe, std::make_index_sequence<N>{});
@@ -665,8 +642,8 @@ __global__ void __launch_bounds__(kBlock, W)
           // b = -(Y - X_m - dtau F(Y)), formed in double
           auto bfn = [&](auto I, TE fi) -> TE {
             constexpr int i = I;
-            using R = ResT<L, i>;
-            return TE(R(L::template at<i>(X[m])) - R(L::template at<i>(Y)) + R(dtau[m]) * R(fi));
+            return TE(double(L::template at<i>(X[m])) - double(L::template at<i>(Y)) +
+                      double(dtau[m]) * double(fi));
           };
           if constexpr (Pol::reuse && m == 1) {
             // the first iteration evaluates at Y = X_1: its rows serve the
@@ -711,12 +688,7 @@ __global__ void __launch_bounds__(kBlock, W)
     if (sd.n_sweeps > 0) {
       for (int k = 0; k < sd.n_sweeps; ++k) {
         static_for<M - 1>([&](auto m) {
-          static_for<N>([&](auto i) {
-            if constexpr (Prec::mixed)
-              Q(m, i) = Sd(m, 0, i) * decltype(Sd(m, 0, i))(F0(i));
-            else
-              Q(m, i) = Sdt[m][0] * double(F0(i));
-          });
+          static_for<N>([&](auto i) { Q(m, i) = Sdt[m][0] * double(F0(i)); });
         });
         // F at nodes 2..M-1 (node 1 comes with its Jacobian below)
         static_for<M - 2>([&](auto JJ) {
@@ -726,12 +698,7 @@ __global__ void __launch_bounds__(kBlock, W)
           if constexpr (Pol::split_evals) opaque(xe);
           eval_F<Model, TE>(p, stim, diff, xe, fj);
           static_for<M - 1>([&](auto m) {
-            static_for<N>([&](auto i) {
-              if constexpr (Prec::mixed)
-                Q(m, i) += Sd(m, jn, i) * decltype(Sd(m, jn, i))(fj[i]);
-              else
-                Q(m, i) += Sdt[m][jn] * double(fj[i]);
-            });
+            static_for<N>([&](auto i) { Q(m, i) += Sdt[m][jn] * double(fj[i]); });
           });
         });
         static_for<M - 1>([&](auto MM) {
@@ -743,24 +710,15 @@ __global__ void __launch_bounds__(kBlock, W)
           // r = X^{k+1}_m - X^k_{m+1} + Q_m in double, formed before the evaluation
           // (Q_m is then dead during it); at m = 0 the evaluation point is node 1,
           // whose F enters every Q_m
-          double r64[L::N64];
-          TE r32[L::N32 > 0 ? L::N32 : 1];
-          auto R0 = [&](auto I) -> ResT<L, decltype(I)::value>& {
-            constexpr int i = decltype(I)::value;
-            if constexpr (i < L::N64)
-              return r64[i];
-            else
-              return r32[i - L::N64];
-          };
+          double r0[N];
           static_for<N>([&](auto I) {
             constexpr int i = I;
-            using R = ResT<L, i>;
-            R0(I) = R(L::template at<i>(X[m])) - R(L::template at<i>(X[m + 1])) + Q(m, I);
+            r0[i] = double(L::template at<i>(X[m])) - double(L::template at<i>(X[m + 1])) + Q(m, i);
           });
           auto bfn = [&](auto I, TE fi) -> TE {
-            using R = ResT<L, decltype(I)::value>;
-            R r = R0(I);
-            if constexpr (m == 0) r += R(Sdt[0][1]) * R(fi);
+            constexpr int i = I;
+            double r = r0[i];
+            if constexpr (m == 0) r += Sdt[0][1] * double(fi);
             return TE(r);
           };
           if constexpr (Pol::reuse && m == 0) {
@@ -778,12 +736,7 @@ __global__ void __launch_bounds__(kBlock, W)
           if constexpr (m == 0) {
             static_for<M - 2>([&](auto MM2) {
               constexpr int mm = MM2 + 1;
-              static_for<N>([&](auto i) {
-                if constexpr (Prec::mixed)
-                  Q(mm, i) += Sd(mm, 1, i) * decltype(Sd(mm, 1, i))(f[i]);
-                else
-                  Q(mm, i) += Sdt[mm][1] * double(f[i]);
-              });
+              static_for<N>([&](auto i) { Q(mm, i) += Sdt[mm][1] * double(f[i]); });
             });
           }
           static_for<N>([&](auto I) {
