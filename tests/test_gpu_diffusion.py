@@ -16,7 +16,10 @@ from paper_2510_27447_amd.workloads import initial_state
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("shape", [(17, 1, 1), (13, 9, 1), (7, 6, 5), (1, 1, 1), (2, 3, 2)])
+# (70, 9, 13): wavefronts of 62 nodes spanning several x-rows and planes;
+# (63, 1, 4100) and (1, 1, 8193): long grids along z, one node wide in y (and x)
+@pytest.mark.parametrize("shape", [(17, 1, 1), (13, 9, 1), (7, 6, 5), (1, 1, 1), (2, 3, 2),
+                                   (70, 9, 13), (63, 1, 4100), (1, 1, 8193)])
 def test_diffusion_current_matches_oracle(shape):
     import torch
     from paper_2510_27447_amd import ionic as I
@@ -25,6 +28,7 @@ def test_diffusion_current_matches_oracle(shape):
     x0 = np.tile(initial_state("TT06")[:, None], (1, n))
     x0[0] = rng.uniform(-85.0, 30.0, n)
     h, sigma = 0.01, 0.75e-3
+    want = Diffusion(shape, h, sigma).current(x0[0])
     for prec in ("fp64", "mixed"):
         sim = I.Simulation("TT06", x0, precision=prec)
         out = torch.zeros(n, dtype=torch.float64, device="cuda")
@@ -32,7 +36,6 @@ def test_diffusion_current_matches_oracle(shape):
         torch.cuda.synchronize()
         got = out.cpu().numpy()
         sim.close()
-        want = Diffusion(shape, h, sigma).current(x0[0])
         scale = max(np.max(np.abs(want)), 1e-300)
         say("grid", shape, prec, "max rel", np.max(np.abs(got - want)) / scale)
         assert np.max(np.abs(got - want)) <= 1e-12 * scale + 1e-300
