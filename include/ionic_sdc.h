@@ -364,7 +364,8 @@ int ionic_elliptic_solve(ionic_sim* sim, const ionic_bidomain_grid* grid, double
 /* Partitioned bidomain stepping, one pass of Algorithm 2 per time step: u
  * from ionic_elliptic_solve with the V field at the start of the step
  * (initial guess: u_dev in the first step, the previous solution in the
- * second, then linear extrapolation from the last two), the current
+ * second, the linear extrapolation from the last two in the third, then the
+ * quadratic extrapolation from the last three), the current
  * -M_L^{-1} A_i (v + u) into i_diff_work_dev (N doubles), held over one
  * reaction step with the handle's predictor.  The
  * parabolic term is explicit in time: dt <= h^2 / (2 max_k sigma_i,k) is

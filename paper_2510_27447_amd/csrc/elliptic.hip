@@ -341,10 +341,13 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 __global__ void __launch_bounds__(kThreads)
-    extrapolate_kernel(CgParams c, double* __restrict__ U, double* __restrict__ u_prev, int first) {
+    extrapolate_kernel(CgParams c, double* __restrict__ U, double* __restrict__ u_prev,
+                       double* __restrict__ u_prev2, int order) {
   for (long long v = my_nodes(c).first, e = my_nodes(c).end; v < e; v += kThreads) {
-    const double u = U[v];
-    if (!first) U[v] = 2.0 * u - u_prev[v];
+    const double u = U[v], u1 = order > 0 ? u_prev[v] : u;
+    if (order == 1) U[v] = 2.0 * u - u1;
+    if (order == 2) U[v] = 3.0 * (u - u1) + u_prev2[v];
+    u_prev2[v] = u1;
     u_prev[v] = u;
   }
 }
@@ -414,9 +417,9 @@ hipError_t cg_remove_mean(const CgParams& c, double* U, CgWork& w, hipStream_t s
   return hipGetLastError();
 }
 
-hipError_t cg_extrapolate(const CgParams& c, double* U, CgWork& w, bool first, hipStream_t st) {
+hipError_t cg_extrapolate(const CgParams& c, double* U, CgWork& w, int order, hipStream_t st) {
   hipLaunchKernelGGL(extrapolate_kernel, dim3(unsigned(c.nb)), dim3(kThreads), 0, st, c, U,
-                     w.u_prev, first ? 1 : 0);
+                     w.u_prev, w.u_prev2, order);
   return hipGetLastError();
 }
 

@@ -43,7 +43,8 @@ struct CgCtl {
 struct CgWork {
   double *r, *z, *q;                 // n each
   double* p[2];                      // n each: p_k is p[k & 1]
-  double* u_prev;                    // n: the previous step's u (time loops)
+  double* u_prev;                    // n: u of the previous step (time loops)
+  double* u_prev2;                   // n: u of the step before it
   double *part_a, *part_b, *part_c;  // one partial sum per block each
   double* sc;
   __host__ __device__ double* p_k(long long k) const { return p[k & 1]; }
@@ -54,7 +55,7 @@ struct CgWork {
   __host__ __device__ double* pq(long long k) { return sc + 8 + 3 * k + 1; }
   __host__ __device__ double* rr(long long k) { return sc + 8 + 3 * k + 2; }
   static size_t bytes(long long n, long long n_parts, int max_iter) {
-    return sizeof(double) * size_t(6 * n + 3 * n_parts + 8 + 3 * (max_iter + 2));
+    return sizeof(double) * size_t(7 * n + 3 * n_parts + 8 + 3 * (max_iter + 2));
   }
 };
 static_assert(sizeof(CgCtl) == 2 * sizeof(double), "CgCtl occupies scalars 3 and 4");
@@ -118,10 +119,11 @@ hipError_t mg_apply(const MgLevels& L, const double* r, double* z, double* xtmp,
                     const double* bb, double rtol, double* rr_out, long long iter,
                     hipStream_t st);
 
-// initial guess of a time loop's next solve: with first, u_prev = U (the guess
-// stays U); otherwise U = 2 U - u_prev and u_prev = the old U (linear
-// extrapolation from the last two solutions)
-hipError_t cg_extrapolate(const CgParams& c, double* U, CgWork& w, bool first, hipStream_t st);
+// initial guess of a time loop's next solve from the last solutions (U holds
+// the last one): order 0 keeps U, order 1 takes 2 U - u_prev (linear), order 2
+// 3 U - 3 u_prev + u_prev2 (quadratic extrapolation); u_prev2 and u_prev then
+// move one step on (u_prev = the old U)
+hipError_t cg_extrapolate(const CgParams& c, double* U, CgWork& w, int order, hipStream_t st);
 hipError_t bidomain_current(const CgParams& c, const double* V, const double* U, double h,
                             double* out, hipStream_t st);
 

@@ -584,7 +584,8 @@ static ionic::CgWork carve_cg_work(void* work, long long n, long long nb) {
   w.p[1] = w.p[0] + n;
   w.q = w.p[1] + n;
   w.u_prev = w.q + n;
-  w.part_a = w.u_prev + n;
+  w.u_prev2 = w.u_prev + n;
+  w.part_a = w.u_prev2 + n;
   w.part_b = w.part_a + nb;
   w.part_c = w.part_b + nb;
   w.sc = w.part_c + nb;
@@ -767,9 +768,9 @@ int reaction_bidomain_step(ionic_sim* s, const ionic_bidomain_grid* g, double t0
   long long expect = 0;
   ionic::CgWork w = carve_cg_work(work_dev, s->n, c.nb);
   for (int k = 0; k < n_steps; ++k) {
-    // the guess: the caller's u, then the last solution, then linear
-    // extrapolation from the last two
-    if (k >= 1) IONIC_HIP(ionic::cg_extrapolate(c, u_dev, w, k == 1, st));
+    // the guess: the caller's u, then the last solution, then the linear
+    // extrapolation from the last two, then the quadratic one from the last three
+    if (k >= 1) IONIC_HIP(ionic::cg_extrapolate(c, u_dev, w, k < 3 ? k - 1 : 2, st));
     const long long before = acc.cg_iterations;
     rc = elliptic_solve_impl(s, c, u_dev, work_dev, rtol, max_iter, pc, &acc, st, expect);
     if (rc != IONIC_OK) return rc;

@@ -171,14 +171,14 @@ def _mg_doubles(shape):
 
 
 def test_elliptic_work_bytes_and_rejections():
-    # 6 vectors, one partial sum per block for 3 quantities (at most 1024 blocks of 256
+    # 7 vectors, one partial sum per block for 3 quantities (at most 1024 blocks of 256
     # threads, a multiple of 8), 8 scalars, 3 per iteration; then the multigrid levels
     n, parts = 100 * 100 * 100, 1024
-    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (6 * n + 3 * parts + 8 + 3 * 52
+    assert I.ionic_elliptic_work_bytes(100, 100, 100, 50) == 8 * (7 * n + 3 * parts + 8 + 3 * 52
                                                                   + _mg_doubles((100, 100, 100)))
     assert _mg_doubles((40, 1, 1)) == 0 and _mg_doubles((9, 8, 5)) == 0  # Jacobi only
-    assert I.ionic_elliptic_work_bytes(40, 1, 1, 10) == 8 * (6 * 40 + 3 * 8 + 8 + 3 * 12)
-    assert I.ionic_elliptic_work_bytes(300, 256, 1, 10) == 8 * (6 * 76800 + 3 * 304 + 8 + 3 * 12
+    assert I.ionic_elliptic_work_bytes(40, 1, 1, 10) == 8 * (7 * 40 + 3 * 8 + 8 + 3 * 12)
+    assert I.ionic_elliptic_work_bytes(300, 256, 1, 10) == 8 * (7 * 76800 + 3 * 304 + 8 + 3 * 12
                                                                 + _mg_doubles((300, 256, 1)))
     assert I.ionic_elliptic_work_bytes(2 ** 16, 2 ** 15, 1, 10) == 0     # 2^31 nodes
     assert I.ionic_elliptic_work_bytes(0, 1, 1, 10) == 0
