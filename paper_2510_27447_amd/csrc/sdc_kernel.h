@@ -294,33 +294,10 @@ struct JacRows {
   static constexpr int kWords = off(N);
 };
 
-// Passes every row on to the inner sink and keeps a copy in a JacRows column.
-template <class Model, class T, class Inner>
-struct SinkRecord {
-  Inner& in;
-  T* col;  // this lane's column: word w at col[w * kBlock]
-  bool rec;
-  template <int i, uint32_t Mx>
-  IONIC_DEV void put(const D<T, Mx>& x) {
-    constexpr int o = JacRows<Model>::off(i);
-    if (rec) {
-    col[o * kBlock] = x.v;
-    for_bits<Model::ROW[i]>([&](auto K) {
-      constexpr int k = K;
-      if constexpr (has(Mx, k))
-        col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = x.template d<k>();
-      else
-        col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = T(0);
-    });
-    }
-    in.template put<i>(x);
-  }
-};
-
 // Keeps the rows in a JacRows column only.
 template <class Model, class T>
 struct SinkKeep {
-  T* col;
+  T* col;  // this lane's column: word w at col[w * kBlock]
   template <int i, uint32_t Mx>
   IONIC_DEV void put(const D<T, Mx>& x) {
     constexpr int o = JacRows<Model>::off(i);
@@ -332,6 +309,20 @@ struct SinkKeep {
       else
         col[(o + 1 + rank(Model::ROW[i], k)) * kBlock] = T(0);
     });
+  }
+};
+
+// Passes every row on to the inner sink and, when rec (uniform over the
+// wavefront), keeps a copy in a JacRows column.
+template <class Model, class T, class Inner>
+struct SinkRecord {
+  Inner& in;
+  SinkKeep<Model, T> keep;
+  bool rec;
+  template <int i, uint32_t Mx>
+  IONIC_DEV void put(const D<T, Mx>& x) {
+    if (rec) keep.template put<i>(x);
+    in.template put<i>(x);
   }
 };
 
@@ -341,7 +332,7 @@ IONIC_DEV void eval_solve_keep(const typename Model::template Params<T>& p, T st
                                const T (&x)[Model::N], BFn bfn, T (&f)[Model::N],
                                T (&delta)[Model::N], T* col, bool rec) {
   SinkElim<Model, T, BFn> s(dtau, bfn);
-  SinkRecord<Model, T, SinkElim<Model, T, BFn>> r{s, col, rec};
+  SinkRecord<Model, T, SinkElim<Model, T, BFn>> r{s, {col}, rec};
   call_rhs_FJ<Model, T>(p, stim, diff, r, x, std::make_index_sequence<Model::N>{});
   s.solve(delta);
   static_for<Model::N>([&](auto I) { f[I] = s.f[I]; });
