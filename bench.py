@@ -634,14 +634,17 @@ def microbench(torch):
 
 
 def run_bidomain_implicit(I, torch, w, n_steps=10, dt=0.05, h=0.01, sigma=1.5e-3,
-                          inner_tol=1e-6, rtol=1e-8, max_iter=2000):
+                          inner_tol=1e-6, rtol=1e-8, max_iter=2000, precision="fp64", ref_V=None):
     """Algorithm 2 in full on the slab (reaction_bidomain_implicit_step): per
     step, inner passes of the elliptic solve and ROS2 + one correction with the
     parabolic term inside the stages, at the paper's largest step dt = 0.05 ms
     (beyond the explicit limit h^2 / (2 sigma_i) = 0.033 ms at h = 0.01 cm),
     stimulus on the first five x-planes for 1 ms.  One untimed run of 2 steps,
-    then one timed run of n_steps from the same state."""
-    sim = I.Simulation(w.model, w.x0, precision="fp64")
+    then one timed run of n_steps from the same state.  precision: the handle's
+    layout (mixed: F, J and the eliminations in float); with ref_V (the V of the
+    fp64 run) the max and RMS of the V difference relative to max|ref_V|.  The
+    returned "_V" is the final V (for the caller, not the JSON line)."""
+    sim = I.Simulation(w.model, w.x0, precision=precision)
     stim = torch.as_tensor(np.where(np.arange(w.n) % w.grid[0] < 5, -100.0, 0.0)).cuda()
     g = I.make_bidomain_grid(*w.grid, h=h, sigma_i=(sigma,) * 3, sigma_e=(sigma,) * 3)
     wb = I.ionic_implicit_work_bytes(w.model, *w.grid, max_iter)
@@ -671,7 +674,8 @@ def run_bidomain_implicit(I, torch, w, n_steps=10, dt=0.05, h=0.01, sigma=1.5e-3
     V = sim.readback(count=None)[0]
     sim.close()
     levels = I.ionic_multigrid_levels(*w.grid)
-    return {
+    out = {
+        "precision": precision,
         "steps": n_steps, "dt_ms": dt, "ms_per_step": wall / n_steps * 1e3,
         "value": w.n * n_steps / wall,
         "inner_passes_per_step": info["inner_passes"] / n_steps, "inner_max": info["inner_max"],
@@ -683,7 +687,12 @@ def run_bidomain_implicit(I, torch, w, n_steps=10, dt=0.05, h=0.01, sigma=1.5e-3
         "launches_per_cycle": 4 * levels - 3 if levels else 0,
         "coarse_level_launches_per_cycle": 4 * levels - 7 if levels else 0,
         "V_range_mV": [float(np.min(V)), float(np.max(V))],
+        "_V": V,
     }
+    if ref_V is not None:
+        d = np.abs(V - ref_V) / np.max(np.abs(ref_V))
+        out["V_error_vs_fp64"] = {"max": float(d.max()), "rms": float(np.sqrt(np.mean(d * d)))}
+    return out
 
 
 def cpu_workers():
@@ -957,6 +966,15 @@ def main():
         bido["implicit"] = run_bidomain_implicit(I, torch, w)
         print("[bench] implicit: %.1f ms per step" % bido["implicit"]["ms_per_step"],
               file=sys.stderr, flush=True)
+        print("[bench] partitioned bidomain, parabolic term implicit, mixed", file=sys.stderr,
+              flush=True)
+        w = W.c2_tt06(precision="mixed")
+        bido["implicit_mixed"] = run_bidomain_implicit(I, torch, w, precision="mixed",
+                                                       ref_V=bido["implicit"]["_V"])
+        print("[bench] implicit mixed: %.1f ms per step" % bido["implicit_mixed"]["ms_per_step"],
+              file=sys.stderr, flush=True)
+        bido["implicit"].pop("_V")
+        bido["implicit_mixed"].pop("_V")
 
     serving = None
     if not args.no_serving:

@@ -409,9 +409,14 @@ size_t ionic_implicit_work_bytes(int model, int64_t nx, int64_t ny, int64_t nz, 
  *         the u of the last step on return.
  *  work_dev: ionic_implicit_work_bytes(model, nx, ny, nz, max_iter) bytes.
  *  max_iter: cap of every CG and BiCGSTAB solve (not an error when reached:
- *         info reports it).  IONIC_FP64 handles only (else
- *         IONIC_EUNSUPPORTED).  Synchronises hip_stream (the host reads each
- *         pass's change). */
+ *         info reports it).  Synchronises hip_stream (the host reads each
+ *         pass's change).
+ * IONIC_MIXED handles: the step runs on a double copy of the state (in the
+ * work buffer), with F, J and the per-vertex eliminations in float and
+ * everything else in double (the states, the right-hand sides including the
+ * correction's residual, BiCGSTAB, the elliptic solve); the result is stored
+ * back in the handle's layout.  inner_tol should then be >= 1e-6, the change
+ * a float F resolves. */
 int reaction_bidomain_implicit_step(ionic_sim* sim, const ionic_bidomain_grid* grid, double t0,
                                     double dt, int n_steps, const double* i_stim_dev,
                                     double stim_t_on, double stim_t_off, double* u_dev,

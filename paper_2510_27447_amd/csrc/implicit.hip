@@ -36,50 +36,55 @@ namespace {
 
 // ---- per-vertex block passes ----------------------------------------------------------
 
-template <class Model>
+// T: the type F, J and the elimination are evaluated in (double, or float for
+// handles in the mixed layout); the states, the right-hand side's base and
+// every output stay double.
+template <class Model, class T>
 struct BlockArgs {
-  typename Model::template Params<double> p;
+  typename Model::template Params<T> p;
   ImpBlock a;
 };
 
-template <class Model>
-__global__ void __launch_bounds__(64, 2) imp_block_kernel(const BlockArgs<Model> args) {
+template <class Model, class T>
+__global__ void __launch_bounds__(64, 2) imp_block_kernel(const BlockArgs<Model, T> args) {
   constexpr int N = Model::N;
   const ImpBlock& a = args.a;
   const long long v = (long long)blockIdx.x * 64 + threadIdx.x;
   const bool active = v < a.n;
   const long long vi = active ? v : a.n - 1;  // tail lanes shadow the last vertex
   const long long st = a.stride;
-  double x[N], base[N];
-  static_for<N>([&](auto I) { x[I] = a.X[I * st + vi]; });
+  T x[N];
+  double base[N];
+  static_for<N>([&](auto I) { x[I] = T(a.X[I * st + vi]); });
   // every input is read before the evaluation, so its rows see no branch
   if (a.base)
     static_for<N>([&](auto I) { base[I] = a.base[I * st + vi]; });
   else
     static_for<N>([&](auto I) { base[I] = 0.0; });
-  const double stim = (a.stim_on && a.stim) ? a.stim[vi] : 0.0;
-  const double diff = a.idiff ? a.idiff[vi] : 0.0;
+  const T stim = T((a.stim_on && a.stim) ? a.stim[vi] : 0.0);
+  const T diff = T(a.idiff ? a.idiff[vi] : 0.0);
   const double cf = a.cf;
-  auto bfn = [&](auto I, double fi) -> double { return cf * fi + base[I]; };
-  SinkSchur<Model, double, decltype(bfn)> s(a.c, bfn);
-  call_rhs_FJ<Model, double>(args.p, stim, diff, s, x, std::make_index_sequence<N>{});
-  double S, r;
+  // the right-hand side formed in double, then taken to T
+  auto bfn = [&](auto I, T fi) -> T { return T(cf * double(fi) + base[I]); };
+  SinkSchur<Model, T, decltype(bfn)> s(T(a.c), bfn);
+  call_rhs_FJ<Model, T>(args.p, stim, diff, s, x, std::make_index_sequence<N>{});
+  T S, r;
   s.reduce(S, r);
   if (!a.expand) {
     if (active) {
-      a.S[v] = S;
-      a.r[v] = r;
+      a.S[v] = double(S);
+      a.r[v] = double(r);
     }
     return;
   }
-  double delta[N];
-  s.expand(a.dv[vi], delta);
-  if (active) static_for<N>([&](auto I) { a.out[I * st + v] = delta[I]; });
+  T delta[N];
+  s.expand(T(a.dv[vi]), delta);
+  if (active) static_for<N>([&](auto I) { a.out[I * st + v] = double(delta[I]); });
 }
 
-template <class Model>
+template <class Model, class T>
 struct RhsArgs {
-  typename Model::template Params<double> p;
+  typename Model::template Params<T> p;
   const double* X;
   long long n, stride;
   const double* stim;
@@ -90,38 +95,38 @@ struct RhsArgs {
   double* out;
 };
 
-template <class Model>
-__global__ void __launch_bounds__(64) imp_rhs_kernel(const RhsArgs<Model> a) {
+template <class Model, class T>
+__global__ void __launch_bounds__(64) imp_rhs_kernel(const RhsArgs<Model, T> a) {
   constexpr int N = Model::N;
   const long long v = (long long)blockIdx.x * 64 + threadIdx.x;
   if (v >= a.n) return;
-  double x[N], f[N];
-  static_for<N>([&](auto I) { x[I] = a.X[I * a.stride + v]; });
-  const double stim = (a.stim_on && a.stim) ? a.stim[v] : 0.0;
-  const double diff = a.idiff ? a.idiff[v] : 0.0;
-  eval_F<Model, double>(a.p, stim, diff, x, f);
+  T x[N], f[N];
+  static_for<N>([&](auto I) { x[I] = T(a.X[I * a.stride + v]); });
+  const T stim = T((a.stim_on && a.stim) ? a.stim[v] : 0.0);
+  const T diff = T(a.idiff ? a.idiff[v] : 0.0);
+  eval_F<Model, T>(a.p, stim, diff, x, f);
   static_for<N>([&](auto I) {
     const double y = a.Y ? a.Y[I * a.stride + v] : 0.0;
-    a.out[I * a.stride + v] = a.alpha * f[I] + a.beta * y;
+    a.out[I * a.stride + v] = a.alpha * double(f[I]) + a.beta * y;
   });
 }
 
-template <class Model>
-hipError_t block_launch(const void* params64, const ImpBlock& a, hipStream_t st) {
-  BlockArgs<Model> args;
-  args.p = *static_cast<const typename Model::template Params<double>*>(params64);
+template <class Model, class T>
+hipError_t block_launch(const void* params, const ImpBlock& a, hipStream_t st) {
+  BlockArgs<Model, T> args;
+  args.p = *static_cast<const typename Model::template Params<T>*>(params);
   args.a = a;
-  hipLaunchKernelGGL(imp_block_kernel<Model>, dim3(unsigned((a.n + 63) / 64)), dim3(64), 0, st,
-                     args);
+  hipLaunchKernelGGL((imp_block_kernel<Model, T>), dim3(unsigned((a.n + 63) / 64)), dim3(64), 0,
+                     st, args);
   return hipGetLastError();
 }
 
-template <class Model>
-hipError_t rhs_launch(const void* params64, const double* X, long long n, long long stride,
+template <class Model, class T>
+hipError_t rhs_launch(const void* params, const double* X, long long n, long long stride,
                       const double* stim, int stim_on, const double* idiff, double alpha,
                       double beta, const double* Y, double* out, hipStream_t st) {
-  RhsArgs<Model> a;
-  a.p = *static_cast<const typename Model::template Params<double>*>(params64);
+  RhsArgs<Model, T> a;
+  a.p = *static_cast<const typename Model::template Params<T>*>(params);
   a.X = X;
   a.n = n;
   a.stride = stride;
@@ -132,7 +137,8 @@ hipError_t rhs_launch(const void* params64, const double* X, long long n, long l
   a.beta = beta;
   a.Y = Y;
   a.out = out;
-  hipLaunchKernelGGL(imp_rhs_kernel<Model>, dim3(unsigned((n + 63) / 64)), dim3(64), 0, st, a);
+  hipLaunchKernelGGL((imp_rhs_kernel<Model, T>), dim3(unsigned((n + 63) / 64)), dim3(64), 0, st,
+                     a);
   return hipGetLastError();
 }
 
@@ -423,26 +429,41 @@ __global__ void __launch_bounds__(kThreads) bicg_upd_kernel(CgParams c, BiCgWork
 
 }  // namespace
 
-hipError_t imp_block(int model, const void* params64, const ImpBlock& a, hipStream_t st) {
+namespace {
+template <class T>
+hipError_t block_for(int model, const void* params, const ImpBlock& a, hipStream_t st) {
   switch (model) {
-    case 1: return block_launch<LR91>(params64, a, st);
-    case 2: return block_launch<TT06>(params64, a, st);
-    case 90: return block_launch<TestLinear>(params64, a, st);
-    case 91: return block_launch<TestLogistic>(params64, a, st);
+    case 1: return block_launch<LR91, T>(params, a, st);
+    case 2: return block_launch<TT06, T>(params, a, st);
+    case 90: return block_launch<TestLinear, T>(params, a, st);
+    case 91: return block_launch<TestLogistic, T>(params, a, st);
     default: return hipErrorInvalidValue;
   }
 }
-
-hipError_t imp_rhs(int model, const void* params64, const double* X, long long n, long long stride,
-                   const double* stim, int stim_on, const double* idiff, double alpha,
-                   double beta, const double* Y, double* out, hipStream_t st) {
+template <class T>
+hipError_t rhs_for(int model, const void* params, const double* X, long long n, long long stride,
+                   const double* stim, int stim_on, const double* idiff, double alpha, double beta,
+                   const double* Y, double* out, hipStream_t st) {
   switch (model) {
-    case 1: return rhs_launch<LR91>(params64, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
-    case 2: return rhs_launch<TT06>(params64, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
-    case 90: return rhs_launch<TestLinear>(params64, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
-    case 91: return rhs_launch<TestLogistic>(params64, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
+    case 1: return rhs_launch<LR91, T>(params, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
+    case 2: return rhs_launch<TT06, T>(params, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
+    case 90: return rhs_launch<TestLinear, T>(params, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
+    case 91: return rhs_launch<TestLogistic, T>(params, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
     default: return hipErrorInvalidValue;
   }
+}
+}  // namespace
+
+hipError_t imp_block(int model, int eval_float, const void* params, const ImpBlock& a,
+                     hipStream_t st) {
+  return eval_float ? block_for<float>(model, params, a, st) : block_for<double>(model, params, a, st);
+}
+
+hipError_t imp_rhs(int model, int eval_float, const void* params, const double* X, long long n,
+                   long long stride, const double* stim, int stim_on, const double* idiff,
+                   double alpha, double beta, const double* Y, double* out, hipStream_t st) {
+  return eval_float ? rhs_for<float>(model, params, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st)
+                    : rhs_for<double>(model, params, X, n, stride, stim, stim_on, idiff, alpha, beta, Y, out, st);
 }
 
 hipError_t soa_lincomb(double* out, const double* x, double a, const double* y, double b,

@@ -32,12 +32,17 @@ struct ImpBlock {
   const double* dv;
   double* out;
 };
-hipError_t imp_block(int model, const void* params64, const ImpBlock& a, hipStream_t st);
+// eval_float: F, J and the elimination in float (params: the model's float
+// parameters), else in double (its double parameters); inputs and outputs are
+// double either way.
+hipError_t imp_block(int model, int eval_float, const void* params, const ImpBlock& a,
+                     hipStream_t st);
 
-// out = alpha F(X) + beta Y (planes; Y may be null when beta = 0)
-hipError_t imp_rhs(int model, const void* params64, const double* X, long long n, long long stride,
-                   const double* stim, int stim_on, const double* idiff, double alpha,
-                   double beta, const double* Y, double* out, hipStream_t st);
+// out = alpha F(X) + beta Y (planes; Y may be null when beta = 0), F evaluated
+// as imp_block's
+hipError_t imp_rhs(int model, int eval_float, const void* params, const double* X, long long n,
+                   long long stride, const double* stim, int stim_on, const double* idiff,
+                   double alpha, double beta, const double* Y, double* out, hipStream_t st);
 
 // out = x + a y + b z over n_states planes of stride elements (z may be null)
 hipError_t soa_lincomb(double* out, const double* x, double a, const double* y, double b,

@@ -799,6 +799,7 @@ namespace {
 struct ImpWork {
   void* elliptic;
   double *XK, *K1, *K2, *XT, *FN, *B;  // state-sized
+  double* XN;  // state-sized: X^n in double planes (handles in the mixed layout)
   double *idiff, *idiff2, *S, *r, *uK;  // fields
   ionic::BiCgWork bw;
   double* xs[3];  // xs[0] is the BiCGSTAB work's own x
@@ -809,7 +810,7 @@ size_t imp_bytes(int n_states, long long nx, long long ny, long long nz, int max
   const long long n = nx * ny * nz, stride = stride_of(n);
   const ionic::CgParams c = ionic::cg_params(nx, ny, nz);
   const size_t ell = (elliptic_bytes(nx, ny, nz, max_iter) + 255) / 256 * 256;
-  return ell + sizeof(double) * size_t(6 * n_states * stride + 5 * stride + 2 * n) +
+  return ell + sizeof(double) * size_t(7 * n_states * stride + 5 * stride + 2 * n) +
          ionic::BiCgWork::bytes(n, c.nb, max_iter) + 256;
 }
 
@@ -821,7 +822,7 @@ ImpWork carve_imp(void* work, int n_states, long long nx, long long ny, long lon
   w.elliptic = work;
   const size_t ell = (elliptic_bytes(nx, ny, nz, max_iter) + 255) / 256 * 256;
   double* q = reinterpret_cast<double*>(static_cast<char*>(work) + ell);
-  double** state_vecs[6] = {&w.XK, &w.K1, &w.K2, &w.XT, &w.FN, &w.B};
+  double** state_vecs[7] = {&w.XK, &w.K1, &w.K2, &w.XT, &w.FN, &w.B, &w.XN};
   for (double** v : state_vecs) {
     *v = q;
     q += size_t(n_states) * size_t(stride);
@@ -904,8 +905,6 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
   if (rc != IONIC_OK) return rc;
   rc = check_step_args(t0, dt, n_steps, 2, 1, stim_t_on, stim_t_off);
   if (rc != IONIC_OK) return rc;
-  if (s->precision != IONIC_FP64)
-    return fail(IONIC_EUNSUPPORTED, "the implicit partitioned step is built for IONIC_FP64");
   if (!u_dev || !work_dev) return fail(IONIC_EINVAL, "u_dev or work_dev is NULL");
   if (!(elliptic_rtol >= 0.0) || !std::isfinite(elliptic_rtol) || !(krylov_rtol >= 0.0) ||
       !std::isfinite(krylov_rtol) || !(inner_tol >= 0.0) || !std::isfinite(inner_tol))
@@ -929,9 +928,15 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
   const long long n = s->n, stride = s->stride;
   const long long elems = (long long)ns * stride;
   const size_t state_bytes = sizeof(double) * size_t(elems);
-  double* Xn = static_cast<double*>(s->state);
+  // the mixed layout: the step runs on a double copy of the state (planes of
+  // stride doubles) with F, J and the eliminations in float, and stores the
+  // result back in the handle's layout at the end
+  const bool mixed = s->precision == IONIC_MIXED;
+  double* Xn = mixed ? w.XN : static_cast<double*>(s->state);
+  if (mixed) IONIC_HIP(s->ops->unpack(IONIC_MIXED, s->state, stride, 0, n, Xn, stride, st));
   const int model = s->model;
-  const void* p64 = s->p64;
+  const int ef = mixed ? 1 : 0;
+  const void* pp = s->params();
   constexpr double kG = ionic::kRosGamma;
   ionic_implicit_info acc{};
   acc.converged = 1;
@@ -959,7 +964,7 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
     b.expand = 0;
     b.S = w.S;
     b.r = w.r;
-    IONIC_HIP(ionic::imp_block(model, p64, b, st));
+    IONIC_HIP(ionic::imp_block(model, ef, pp, b, st));
     int rc2 = bicg_solve(ck, g->h, c, w, sys, have_guess[sys], krylov_last[sys], max_iter, &acc,
                          &krylov_last[sys], st);
     if (rc2 != IONIC_OK) return rc2;
@@ -967,7 +972,7 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
     b.expand = 1;
     b.dv = w.xs[sys];
     b.out = out;
-    IONIC_HIP(ionic::imp_block(model, p64, b, st));
+    IONIC_HIP(ionic::imp_block(model, ef, pp, b, st));
     return IONIC_OK;
   };
 
@@ -976,7 +981,7 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
     const int on = (stim_t_on <= t_mid && t_mid < stim_t_off) ? 1 : 0;
     // G(X^n; u^n) for the correction
     IONIC_HIP(ionic::bidomain_current(ce, Xn, u_dev, g->h, w.idiff, st));
-    IONIC_HIP(ionic::imp_rhs(model, p64, Xn, n, stride, i_stim_dev, on, w.idiff, 1.0, 0.0, nullptr,
+    IONIC_HIP(ionic::imp_rhs(model, ef, pp, Xn, n, stride, i_stim_dev, on, w.idiff, 1.0, 0.0, nullptr,
                              w.FN, st));
     IONIC_HIP(hipMemcpyAsync(w.XK, Xn, state_bytes, hipMemcpyDeviceToDevice, st));
     IONIC_HIP(hipMemcpyAsync(w.uK, u_dev, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, st));
@@ -996,7 +1001,7 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
       if (rc != IONIC_OK) return rc;
       IONIC_HIP(ionic::soa_lincomb(w.XT, Xn, ionic::kRosA21, w.K1, 0.0, nullptr, elems, st));
       IONIC_HIP(ionic::bidomain_current(ce, w.XT, w.uK, g->h, w.idiff2, st));
-      IONIC_HIP(ionic::imp_rhs(model, p64, w.XT, n, stride, i_stim_dev, on, w.idiff2, kG * dt,
+      IONIC_HIP(ionic::imp_rhs(model, ef, pp, w.XT, n, stride, i_stim_dev, on, w.idiff2, kG * dt,
                                -2.0, w.K1, w.B, st));
       rc = stage(1, Xn, kG * dt, 0.0, w.B, w.idiff, on, w.K2);
       if (rc != IONIC_OK) return rc;
@@ -1023,6 +1028,7 @@ int reaction_bidomain_implicit_step(ionic_sim* s, const ionic_bidomain_grid* g, 
     IONIC_HIP(hipMemcpyAsync(Xn, w.XK, state_bytes, hipMemcpyDeviceToDevice, st));
     IONIC_HIP(hipMemcpyAsync(u_dev, w.uK, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, st));
   }
+  if (mixed) IONIC_HIP(s->ops->pack(IONIC_MIXED, Xn, stride, s->state, stride, 0, n, st));
   IONIC_HIP(hipStreamSynchronize(st));
   acc.cg_iterations = ell.cg_iterations;
   if (info) *info = acc;

@@ -27,7 +27,7 @@ SIG = (1.5e-3,) * 3
 
 
 def run_both(model, x0, shape, stim, n_steps, dt=0.05, h=0.01, precision="fp64", params=None,
-             t_off=1.0):
+             t_off=1.0, gpu_rtol=1e-13, gpu_inner_tol=1e-12):
     import torch
     from paper_2510_27447_amd import ionic as I
     n = x0.shape[1]
@@ -46,9 +46,9 @@ def run_both(model, x0, shape, stim, n_steps, dt=0.05, h=0.01, precision="fp64",
     work = torch.zeros(wb, dtype=torch.uint8, device="cuda")
     g = I.make_bidomain_grid(*shape, h=h, sigma_i=SIG, sigma_e=SIG)
     info = I.reaction_bidomain_implicit_step(sim.handle, g, 0.0, dt, n_steps, u, work, wb,
-                                             gpu_tensor(stim), 0.0, t_off, elliptic_rtol=1e-13,
-                                             krylov_rtol=1e-13, inner_tol=1e-12, max_inner=60,
-                                             max_iter=max_iter)
+                                             gpu_tensor(stim), 0.0, t_off, elliptic_rtol=gpu_rtol,
+                                             krylov_rtol=gpu_rtol, inner_tol=gpu_inner_tol,
+                                             max_inner=60, max_iter=max_iter)
     Xg = sim.readback()
     ug = u.cpu().numpy()
     sim.close()
@@ -82,6 +82,37 @@ def test_implicit_partitioned_matches_oracle(model, shape):
     assert info["converged"] == 1 and info["krylov_converged"] == 1
     assert np.all(np.isfinite(Xg))
     check(model, Xg, Xo, ug, uo)
+
+
+@pytest.mark.parametrize("model", ["LR91", "TT06"])
+@pytest.mark.parametrize("shape", [(12, 10, 1), (6, 5, 4)], ids=["sheet", "slab"])
+def test_implicit_partitioned_mixed_matches_oracle(model, shape):
+    """Handles in the mixed layout: F, J and the eliminations in float, states,
+    residuals and the solves in double.  The GPU stops its inner loop at a
+    scaled change of 1e-6 (what a float F resolves) and its solves at 1e-10;
+    the oracle runs as above.  Bars of the mixed path: V and the double-held
+    concentrations within 1e-4 of their scale, every state within 1e-3, u within
+    1e-4 of max|u|."""
+    n = int(np.prod(shape))
+    rng = np.random.Generator(np.random.PCG64(31))
+    x0 = np.tile(initial_state(model)[:, None], (1, n))
+    x0[0] += rng.uniform(-1.0, 1.0, n)
+    stim = np.where(np.arange(n) % shape[0] < 2, -100.0, 0.0)
+    say("case mixed", model, shape)
+    Xo, uo, st, Xg, ug, info = run_both(model, x0, shape, stim, n_steps=12, precision="mixed",
+                                        gpu_rtol=1e-10, gpu_inner_tol=1e-6)
+    say("  gpu", info, "oracle passes", st.inner_iterations)
+    assert info["converged"] == 1 and info["krylov_converged"] == 1
+    assert np.all(np.isfinite(Xg))
+    mdl = MODEL_OF[model]
+    n64 = 2 if model == "LR91" else 6
+    scale = np.maximum(np.max(np.abs(Xo), axis=1), mdl.newton_scale)
+    serr = np.max(np.abs(Xg - Xo), axis=1) / scale
+    eu = np.max(np.abs(ug - uo)) / max(np.max(np.abs(uo)), 1e-300)
+    say("  V %.2e, double-held %.2e, worst state %.2e, u %.2e" % (serr[0], serr[:n64].max(),
+                                                                 serr.max(), eu))
+    assert np.all(serr[:n64] <= 1e-4) and np.all(serr <= 1e-3), serr
+    assert eu <= 1e-4
 
 
 @pytest.mark.parametrize("k", [1, 16, 32])
