@@ -40,7 +40,9 @@ def run(model, precision, pred, M, K, x0, stim, diff, order=None, dt=0.02, n_ste
 
 @pytest.mark.parametrize("model,precision,M,pred", [
     ("TT06", "mixed", 3, "newton"), ("TT06", "fp64", 3, "newton"), ("TT06", "mixed", 3, "rush_larsen"),
-    ("TT06", "mixed", 2, "ros2"), ("LR91", "fp64", 3, "newton"), ("LR91", "mixed", 2, "ros2")])
+    ("TT06", "mixed", 2, "ros2"), ("LR91", "fp64", 3, "newton"), ("LR91", "mixed", 2, "ros2"),
+    # kernels that keep the predictor's rows at node 1 in LDS for the first sweep
+    ("TT06", "mixed", 4, "newton"), ("LR91", "mixed", 3, "newton")])
 @pytest.mark.parametrize("shape", [(13, 11, 9), (64, 64, 33)], ids=["small", "two_wave"])
 def test_order_changes_nothing(model, precision, M, pred, shape):
     n = int(np.prod(shape))
